@@ -1,0 +1,181 @@
+/*
+ * lsb_oracle.c -- plain, bit-by-bit CPU oracle (see lsb_oracle.h).
+ *
+ * TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Written for a reader who checks it
+ * against the paper by eye: one stream bit at a time, no blocking, no tables.
+ *
+ * Paper passages followed:
+ *   Section VI step 7 (embedding): per cover byte, keep the bits outside the
+ *     field (the paper's mask 1111 1100), OR in the data bits (its masks
+ *     0000 0011 .. 1100 0000 shifted right by 2i).  Generalised to k bits.
+ *   Section VI step 5 / Section VII step 4: the data must fit; at 2 bits per
+ *     cover byte one data byte needs 4 cover bytes, i.e. n*k/8 stream bytes
+ *     fit an n-byte cover in general.
+ *   Section VII step 6 (extraction): mask the field (0000 0011), shift it to
+ *     its place in the data byte and OR it into the zero-initialised byte.
+ * Readings (paper silent): MSB-first stream, BE32 length header, sequential
+ * placement over every channel byte, partial last field keeps the cover's
+ * remaining low bits, bytes past the stream unchanged.
+ */
+#include "lsb_oracle.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+/* Bit j of a byte string read most-significant bit first. */
+static unsigned get_bit(const uint8_t *bytes, uint64_t j)
+{
+    return (bytes[j / 8] >> (7 - (j % 8))) & 1u;
+}
+
+static void set_bit(uint8_t *bytes, uint64_t j, unsigned bit)
+{
+    if (bit)
+        bytes[j / 8] |= (uint8_t)(0x80u >> (j % 8));
+}
+
+/* floor(n*k/8) without overflowing 64 bits. */
+static uint64_t bits_to_bytes_floor(uint64_t n, int k)
+{
+    return (n / 8) * (uint64_t)k + ((n % 8) * (uint64_t)k) / 8;
+}
+
+int64_t oracle_capacity(uint64_t n, int k)
+{
+    if (k < 1 || k > 8)
+        return ORACLE_E_ARG;
+    uint64_t room = bits_to_bytes_floor(n, k); /* whole stream bytes that fit */
+    if (room < 4)
+        return ORACLE_E_CAPACITY;
+    uint64_t cap = room - 4;
+    if (cap > 0xFFFFFFFFull)
+        cap = 0xFFFFFFFFull;
+    return (int64_t)cap;
+}
+
+int oracle_embed_raw(const uint8_t *cover, uint8_t *stego, uint64_t n,
+                     uint64_t t0, const uint8_t *stream, uint64_t stream_bits,
+                     int k)
+{
+    if (k < 1 || k > 8)
+        return ORACLE_E_ARG;
+    if (n > 0 && (!cover || !stego))
+        return ORACLE_E_ARG;
+    if (stream_bits > 0 && !stream)
+        return ORACLE_E_ARG;
+
+    for (uint64_t t = 0; t < n; ++t) {
+        uint64_t first = (uint64_t)k * (t0 + t); /* first stream bit of field */
+        if (first >= stream_bits) {
+            stego[t] = cover[t]; /* past the stream: unchanged */
+            continue;
+        }
+        uint64_t left = stream_bits - first;
+        unsigned nb = left < (uint64_t)k ? (unsigned)left : (unsigned)k;
+        /* v = the nb stream bits, first bit most significant */
+        unsigned v = 0;
+        for (unsigned q = 0; q < nb; ++q)
+            v = (v << 1) | get_bit(stream, first + q);
+        /* the nb bits occupy the top of the k-bit field */
+        unsigned shift = (unsigned)k - nb;
+        unsigned mask = ((1u << nb) - 1u) << shift;
+        stego[t] = (uint8_t)((cover[t] & ~mask & 0xFFu) | (v << shift));
+    }
+    return ORACLE_OK;
+}
+
+int oracle_extract_raw(const uint8_t *stego, uint64_t n, uint64_t t0,
+                       uint8_t *stream_out, uint64_t stream_bits, int k)
+{
+    if (k < 1 || k > 8)
+        return ORACLE_E_ARG;
+    uint64_t begin = (uint64_t)k * t0;
+    uint64_t end = (uint64_t)k * (t0 + n);
+    if (end > stream_bits)
+        end = stream_bits;
+    if (begin % 8 != 0)
+        return ORACLE_E_ARG;
+    if (begin >= end)
+        return ORACLE_OK; /* this slice carries no stream bits */
+    if (end % 8 != 0 && end != stream_bits)
+        return ORACLE_E_ARG;
+    if (!stego || !stream_out)
+        return ORACLE_E_ARG;
+
+    /* zero-initialise the output bytes (Section VII step 4), then OR bits in */
+    uint64_t first_byte = begin / 8;
+    uint64_t last_byte = (end + 7) / 8; /* exclusive */
+    memset(stream_out + first_byte, 0, (size_t)(last_byte - first_byte));
+    for (uint64_t j = begin; j < end; ++j) {
+        uint64_t t = j / (uint64_t)k - t0; /* field holding stream bit j */
+        unsigned q = (unsigned)(j % (uint64_t)k); /* its place in the field */
+        unsigned bit = (stego[t] >> ((unsigned)k - 1 - q)) & 1u;
+        set_bit(stream_out, j, bit);
+    }
+    return ORACLE_OK;
+}
+
+int oracle_embed(const uint8_t *cover, uint8_t *stego, uint64_t n,
+                 const uint8_t *msg, uint32_t len, int k)
+{
+    int64_t cap = oracle_capacity(n, k);
+    if (cap < 0)
+        return (int)cap;
+    if ((uint64_t)len > (uint64_t)cap)
+        return ORACLE_E_CAPACITY;
+    if (len > 0 && !msg)
+        return ORACLE_E_ARG;
+
+    /* S = BE32(len) || msg, assembled explicitly */
+    uint64_t s_bytes = 4 + (uint64_t)len;
+    uint8_t *s = (uint8_t *)malloc((size_t)s_bytes);
+    if (!s)
+        return ORACLE_E_NOMEM;
+    s[0] = (uint8_t)(len >> 24);
+    s[1] = (uint8_t)(len >> 16);
+    s[2] = (uint8_t)(len >> 8);
+    s[3] = (uint8_t)len;
+    if (len > 0)
+        memcpy(s + 4, msg, len);
+    int rc = oracle_embed_raw(cover, stego, n, 0, s, 8 * s_bytes, k);
+    free(s);
+    return rc;
+}
+
+int oracle_extract(const uint8_t *stego, uint64_t n, int k,
+                   uint8_t *msg_out, uint64_t out_cap, uint32_t *len_out)
+{
+    if (k < 1 || k > 8 || !len_out)
+        return ORACLE_E_ARG;
+    *len_out = 0;
+    uint64_t cover_bits = (uint64_t)k * n;
+    if (cover_bits < 32)
+        return ORACLE_E_HEADER; /* not even the header fits */
+
+    /* header: stream bits 0..31, a big-endian byte count */
+    uint8_t hdr[4];
+    int rc = oracle_extract_raw(stego, n, 0, hdr, 32, k);
+    if (rc != ORACLE_OK)
+        return rc;
+    uint32_t len = ((uint32_t)hdr[0] << 24) | ((uint32_t)hdr[1] << 16) |
+                   ((uint32_t)hdr[2] << 8) | (uint32_t)hdr[3];
+    *len_out = len;
+    if (4 + (uint64_t)len > bits_to_bytes_floor(n, k))
+        return ORACLE_E_HEADER;
+    if ((uint64_t)len > out_cap)
+        return ORACLE_E_BUFFER;
+    if (len == 0)
+        return ORACLE_OK;
+    if (!msg_out)
+        return ORACLE_E_ARG;
+
+    uint64_t s_bytes = 4 + (uint64_t)len;
+    uint8_t *s = (uint8_t *)malloc((size_t)s_bytes);
+    if (!s)
+        return ORACLE_E_NOMEM;
+    rc = oracle_extract_raw(stego, n, 0, s, 8 * s_bytes, k);
+    if (rc == ORACLE_OK)
+        memcpy(msg_out, s + 4, len);
+    free(s);
+    return rc;
+}

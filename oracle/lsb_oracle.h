@@ -1,0 +1,80 @@
+/*
+ * lsb_oracle.h -- CPU oracle for k-bit LSB embedding and extraction.
+ *
+ * TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only the test suite, the smoke
+ * check and the benchmark's CPU-baseline leg may load or call this library.
+ * It shares no code, header, table or constant with the GPU library.
+ *
+ * What it computes (Patel, Pradhan, Ambegaokar, "A Novel Approach for
+ * Implementing Steganography ...", arXiv:0912.0947):
+ *   - embedding, Section VI step 7: clear the low bits of a cover byte and
+ *     OR in a piece of a data byte (the paper fixes 2 bits; here k = 1..8);
+ *   - extraction, Section VII step 6: mask the low bits of a stego byte,
+ *     shift them into place and OR them into the zero-initialised data byte.
+ *
+ * Readings where the paper is silent (each listed in the design notes):
+ *   - the bit stream is S = BE32(len) || msg, read most-significant bit first;
+ *   - cover byte t (flat HWC raster order, every channel byte) carries stream
+ *     bits k*t .. k*t+k-1, the first of them in the highest bit of the field;
+ *   - the last field may carry nb < k bits: only its top nb field bits change;
+ *   - cover bytes past the stream are left unchanged.
+ *
+ * All functions are synchronous, operate on host memory and never allocate
+ * memory visible to the caller.  Return codes are ORACLE_* below.
+ */
+#ifndef LSB_ORACLE_H
+#define LSB_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ORACLE_OK = 0,
+    ORACLE_E_ARG = -1,       /* bad k, null pointer, misaligned raw slice   */
+    ORACLE_E_CAPACITY = -2,  /* message does not fit the cover              */
+    ORACLE_E_HEADER = -3,    /* decoded length does not fit the stego cover */
+    ORACLE_E_BUFFER = -4,    /* decoded length exceeds the output buffer    */
+    ORACLE_E_NOMEM = -6
+};
+
+/* Message capacity in bytes of an n-byte cover at k bits per byte:
+ * floor(n*k/8) - 4 (four bytes go to the length header), capped at 2^32-1.
+ * ORACLE_E_ARG if k is outside 1..8, ORACLE_E_CAPACITY if floor(n*k/8) < 4. */
+int64_t oracle_capacity(uint64_t n, int k);
+
+/* Header-mode embed: stego[0..n) <- cover with S = BE32(len)||msg written
+ * into the low k bits.  stego may equal cover (in place).  On any error the
+ * output is left untouched. */
+int oracle_embed(const uint8_t *cover, uint8_t *stego, uint64_t n,
+                 const uint8_t *msg, uint32_t len, int k);
+
+/* Header-mode extract: decode len from the first 32 stream bits, then the
+ * message.  *len_out receives the decoded length whenever the 32 header bits
+ * fit the cover (also on ORACLE_E_HEADER / ORACLE_E_BUFFER), else 0.  msg_out
+ * is written only on ORACLE_OK. */
+int oracle_extract(const uint8_t *stego, uint64_t n, int k,
+                   uint8_t *msg_out, uint64_t out_cap, uint32_t *len_out);
+
+/* Raw slice embed.  The buffer holds cover bytes [t0, t0+n) of a logical
+ * cover; `stream` is byte 0 of the logical stream of `stream_bits` bits.
+ * Byte t of the buffer carries stream bits k*(t0+t) .. k*(t0+t)+k-1. */
+int oracle_embed_raw(const uint8_t *cover, uint8_t *stego, uint64_t n,
+                     uint64_t t0, const uint8_t *stream, uint64_t stream_bits,
+                     int k);
+
+/* Raw slice extract: writes stream bits [k*t0, e), e = min(k*(t0+n),
+ * stream_bits), into stream_out (byte 0 = logical stream byte 0), bytes
+ * k*t0/8 .. ceil(e/8)-1.  Bits at or past stream_bits in the last byte are
+ * written as zero.  Requires k*t0 % 8 == 0, and e % 8 == 0 unless
+ * e == stream_bits (ORACLE_E_ARG otherwise), so that no output byte is
+ * shared with a neighbouring slice. */
+int oracle_extract_raw(const uint8_t *stego, uint64_t n, uint64_t t0,
+                       uint8_t *stream_out, uint64_t stream_bits, int k);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
