@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Benchmark of the LSB embed/extract hot path on one MI355X.
+
+Step = one pass of the hot path over the large-image workload: an
+8192x8192x3 uint8 smooth cover (201,326,592 bytes) with a message filling
+its full capacity at k = 1, 2 and 4; for each k one embed launch and one
+extract launch (the extract decodes the length header on the device).  All
+inputs are resident in HBM before the timed region.  Three rotating buffer
+sets (about 3 GB touched per step) keep the 256 MB Infinity Cache from
+serving repeated reads.
+
+value = algorithmic bytes of all launches of the K timed steps / wall time
+(embed: 2n + |S|, extract: F + len, |S| = 4 + len, F = ceil(8|S|/k)).
+
+Prints ONE JSON line (plus optional extra lines with --verbose on stderr).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "embed+extract GB/s vs HBM peak; batched vs per-image plain; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+H, W, C = 8192, 8192, 3
+KS = (1, 2, 4)
+SETS = 3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def embed_bytes(n, ln):
+    return 2 * n + 4 + ln
+
+
+def extract_bytes(n, ln, k):
+    s = 4 + ln
+    return -(-8 * s // k) + ln
+
+
+def cpu_baseline(cover_np, msgs):
+    """The oracle as it stands, single-threaded, on one full step of the
+    workload (embed + extract at k = 1, 2, 4 on the whole cover)."""
+    import oracle
+
+    n = cover_np.size
+    total = 0
+    t0 = time.perf_counter()
+    for k in KS:
+        msg = msgs[k]
+        rc, stego = oracle.embed(cover_np, msg, k)
+        assert rc == 0
+        rc, ln, out = oracle.extract(stego, k)
+        assert rc == 0 and ln == msg.size
+        total += embed_bytes(n, msg.size) + extract_bytes(n, msg.size, k)
+    dt = time.perf_counter() - t0
+    return {"value": round(total / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "one full step: embed+extract at k=1,2,4 of the 8192x8192x3 cover on host "
+                      "buffers (%.1f s), single thread" % dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--verbose", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would take "
+              "its own covers or byte-range shards independently); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_0912_0947_amd import api, inputs
+    from paper_0912_0947_amd._lib import lib
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    lib()  # fails loudly if liblsb.so is missing
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    log("generating 8192x8192x3 smooth cover ...")
+    cover_np = inputs.smooth_cover(H, W, C).reshape(-1)
+    n = cover_np.size
+    msgs_np = {k: inputs.random_bytes(api.capacity(n, k), 203, k) for k in KS}
+
+    covers = [torch.from_numpy(cover_np).to(dev) for _ in range(SETS)]
+    msgs = {k: torch.from_numpy(m).to(dev) for k, m in msgs_np.items()}
+    stegos = {k: [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(SETS)] for k in KS}
+    outs = {k: [torch.empty(msgs_np[k].size, dtype=torch.uint8, device=dev) for _ in range(SETS)] for k in KS}
+    ls = torch.zeros((len(KS), SETS, 2), dtype=torch.int32, device=dev)
+    for k in KS:  # every stego buffer holds a valid stream before timing
+        for j in range(SETS):
+            api.embed(covers[j], msgs[k], k, out=stegos[k][j])
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    step_bytes = sum(embed_bytes(n, msgs_np[k].size) + extract_bytes(n, msgs_np[k].size, k) for k in KS)
+
+    def step(it, events=None):
+        j = it % SETS
+        jx = (it + 1) % SETS  # extract reads a stego written an earlier step
+        for ki, k in enumerate(KS):
+            if events is not None:
+                events[("embed", k)][0].record(stream)
+            api.embed(covers[j], msgs[k], k, out=stegos[k][j])
+            if events is not None:
+                events[("embed", k)][1].record(stream)
+                events[("extract", k)][0].record(stream)
+            api.extract(stegos[k][jx], k, out=outs[k][jx], len_status=ls[ki, jx])
+            if events is not None:
+                events[("extract", k)][1].record(stream)
+
+    for it in range(args.warmup):
+        step(it)
+    torch.cuda.synchronize()
+
+    # timed region: K steps, per-launch HIP events on the launch stream
+    ev = [{(op, k): (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for op in ("embed", "extract") for k in KS} for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(args.steps):
+        step(args.warmup + it, ev[it])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    # correctness of the last step's outputs (device-side compare, no copies)
+    st = ls.cpu().numpy()
+    for ki, k in enumerate(KS):
+        for j in range(SETS):
+            assert st[ki, j, 1] == 0 and st[ki, j, 0] == msgs_np[k].size, (k, j, st[ki, j])
+        assert torch.equal(outs[k][(args.warmup + args.steps) % SETS], msgs[k]), "extract mismatch k=%d" % k
+
+    per = {}
+    for (op, k) in ev[0]:
+        ms = [e[(op, k)][0].elapsed_time(e[(op, k)][1]) for e in ev]
+        ln = msgs_np[k].size
+        b = embed_bytes(n, ln) if op == "embed" else extract_bytes(n, ln, k)
+        med = statistics.median(ms)
+        per["%s_k%d" % (op, k)] = {"bytes": b, "us_median": round(med * 1e3, 2), "us_min": round(min(ms) * 1e3, 2),
+                                   "us_mean": round(statistics.fmean(ms) * 1e3, 2),
+                                   "GBps_median": round(b / (med * 1e-3) / 1e9, 1)}
+    value = step_bytes * args.steps / wall / 1e9
+    dom = per["embed_k1"]
+    achieved = dom["bytes"] / (dom["us_mean"] * 1e-6) / 1e9
+    traffic = None
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "lsb_embed_kernel<1,*,*> (k=1 embed, 8192x8192x3, full capacity)",
+                "algorithmic_bytes_per_launch": dom["bytes"]}
+
+    result = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "large image: 8192x8192x3 uint8 smooth cover (201,326,592 B), message at full "
+                               "capacity, k=1,2,4, one embed + one extract launch per k per step",
+                   "cover_bytes": n, "ks": list(KS), "buffer_sets": SETS},
+        "roofline": roofline,
+        "per_launch": per,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on one step ...")
+        result["cpu_baseline"] = cpu_baseline(cover_np, msgs_np)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

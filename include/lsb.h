@@ -1,0 +1,202 @@
+/*
+ * lsb.h -- C ABI of liblsb.so: k-bit least-significant-bit embedding and
+ * extraction on AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the one of Patel, Pradhan and Ambegaokar, "A Novel
+ * Approach for Implementing Steganography with Computing Power Obtained by
+ * Combining CUDA and MATLAB" (arXiv:0912.0947):
+ *   - embedding (Section VI, step 7): each cover byte keeps its high bits and
+ *     takes a piece of the data in its low bits (the paper: 2 bits, masks
+ *     1111 1100 / 0000 0011); here the field width k is a parameter, 1..8;
+ *   - extraction (Section VII, step 6): the low bits of each stego byte are
+ *     masked, shifted into place and ORed into zero-initialised data bytes;
+ *   - capacity (Section VI step 5, Section VII step 4): at 2 bits per byte a
+ *     data byte needs 4 cover bytes; in general n cover bytes hold n*k bits.
+ *
+ * Readings fixed by this library where the paper is silent:
+ *   - stream S = BE32(len) || msg: a 32-bit big-endian byte count, then the
+ *     message; bits are read most-significant first;
+ *   - cover layout: flat bytes (an HWC image or video frame in raster order,
+ *     every channel byte carries data); cover byte t carries stream bits
+ *     k*t .. k*t+k-1, the first of them in the highest bit of the k-bit field;
+ *   - F = ceil(8*|S| / k) cover bytes carry the stream; if k does not divide
+ *     8*|S|, the last field carries nb < k bits in its top nb bits and keeps
+ *     the cover's other low bits; bytes t >= F are copied unchanged.
+ *
+ * Conventions for every call below:
+ *   - Buffer pointers are DEVICE pointers owned by the caller (for example
+ *     torch uint8 tensors on the GPU); the library never frees them.  Plain
+ *     embed/extract calls never allocate.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls enqueue work and return after host-side validation; results are
+ *     ready once the stream reaches that point.
+ *   - Return value: LSB_OK (0) once enqueued, or a negative LSB_E_* code, in
+ *     which case nothing was enqueued and outputs are untouched.  No C++
+ *     exception crosses the ABI.  lsb_last_error() gives a message for the
+ *     last failed call on the calling thread.
+ *   - Any alignment is accepted.  The fast kernels need the cover and stego
+ *     (or stego) pointers 16-byte aligned; otherwise a per-byte kernel runs
+ *     (same results, lower bandwidth).
+ */
+#ifndef LSB_H
+#define LSB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LSB_OK = 0,
+    LSB_E_ARG = -1,      /* bad argument: k outside 1..8, null or overlapping buffers */
+    LSB_E_CAPACITY = -2, /* message longer than the cover can hold */
+    LSB_E_HEADER = -3,   /* decoded length does not fit the stego cover */
+    LSB_E_BUFFER = -4,   /* decoded length exceeds the output buffer */
+    LSB_E_HIP = -5,      /* a HIP runtime call failed */
+    LSB_E_NOMEM = -6     /* a plan or graph could not be allocated */
+};
+
+enum { LSB_OP_EMBED = 0, LSB_OP_EXTRACT = 1 };
+
+/* Message capacity in bytes of an n-byte cover at k bits per byte:
+ * floor(n*k/8) - 4, capped at 2^32 - 1 by the header width (Section VI step 5
+ * generalised).  LSB_E_ARG if k is outside 1..8; LSB_E_CAPACITY if
+ * floor(n*k/8) < 4.  Host-only; touches no GPU. */
+int64_t lsb_capacity(uint64_t n, int k);
+
+/* Embed msg[0..len) into cover[0..n) at k bits per byte, writing
+ * stego[0..n) (Section VI step 7).  stego == cover is the in-place form: only
+ * bytes t < F are rewritten.  Any other overlap between cover, stego and msg
+ * is LSB_E_ARG.  len > lsb_capacity(n, k) is LSB_E_CAPACITY. */
+int lsb_embed(const uint8_t *cover, uint8_t *stego, uint64_t n,
+              const uint8_t *msg, uint32_t len, int k, void *stream);
+
+/* Extract the message from stego[0..n) (Section VII step 6).  The 32-bit
+ * header is decoded on the device; nothing returns to the host.  When the
+ * stream is done: *len_out_dev = decoded length (0 if n*k < 32) and
+ * *status_out_dev = LSB_OK, LSB_E_HEADER (length does not fit the cover;
+ * msg_out untouched) or LSB_E_BUFFER (length > out_cap; msg_out untouched).
+ * msg_out may be NULL when out_cap == 0. */
+int lsb_extract(const uint8_t *stego, uint64_t n, int k, uint8_t *msg_out,
+                uint64_t out_cap, uint32_t *len_out_dev,
+                int32_t *status_out_dev, void *stream);
+
+/* As lsb_extract, then waits for the stream and returns the device status
+ * as the return value (LSB_OK, LSB_E_HEADER, LSB_E_BUFFER) with the decoded
+ * length in *len_out_host.  Uses a small per-thread device buffer that is
+ * allocated on the first call. */
+int lsb_extract_sync(const uint8_t *stego, uint64_t n, int k,
+                     uint8_t *msg_out, uint64_t out_cap,
+                     uint32_t *len_out_host, void *stream);
+
+/* Raw slices: no header.  The buffer holds cover bytes [t0, t0+n) of a
+ * longer logical cover (one video frame of a clip, one shard of a cover);
+ * `stream_bytes` points at byte 0 of a logical stream of `stream_bits` bits.
+ * Buffer byte t carries stream bits k*(t0+t) .. k*(t0+t)+k-1.
+ *
+ * lsb_embed_raw: stego[t] as in lsb_embed for stream bits < stream_bits,
+ * cover[t] past them; any t0.  Reads stream bytes k*t0/8 onwards only.
+ *
+ * lsb_extract_raw: writes stream bits [k*t0, e), e = min(k*(t0+n),
+ * stream_bits), into stream_out (byte 0 = logical byte 0), i.e. bytes
+ * k*t0/8 .. ceil(e/8)-1, pad bits past stream_bits as zero.  Requires
+ * k*t0 % 8 == 0 and (e % 8 == 0 or e == stream_bits), so that slices never
+ * share an output byte; LSB_E_ARG otherwise. */
+int lsb_embed_raw(const uint8_t *cover, uint8_t *stego, uint64_t n,
+                  uint64_t t0, const uint8_t *stream_bytes,
+                  uint64_t stream_bits, int k, void *stream);
+int lsb_extract_raw(const uint8_t *stego, uint64_t n, uint64_t t0,
+                    uint8_t *stream_out, uint64_t stream_bits, int k,
+                    void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched form: thousands of covers of uneven size and k in one persistent
+ * launch (the paper's per-row loop over an image, Section VI steps 4-5, and
+ * its frame loop over a video, generalised to independent covers).
+ *
+ * A job names byte offsets into three caller-owned device arenas.  Every
+ * offset must be a multiple of 256 (LSB_E_ARG otherwise).  The caller
+ * guarantees that each job's buffers lie inside the arenas and that no job
+ * writes bytes another job reads or writes.
+ */
+typedef struct lsb_job {
+    uint64_t cover_off; /* embed: cover input (cover arena)                  */
+    uint64_t stego_off; /* embed: stego output; extract: stego input         */
+    uint64_t msg_off;   /* embed: message input; extract: message output     */
+    uint64_t n;         /* cover bytes                                       */
+    uint64_t msg_cap;   /* extract: output capacity in bytes (embed: unused) */
+    uint32_t len;       /* embed: message length (extract: unused)           */
+    uint8_t k;          /* bits per cover byte, 1..8                         */
+    uint8_t op;         /* LSB_OP_EMBED or LSB_OP_EXTRACT                    */
+    uint16_t reserved;  /* must be 0                                         */
+} lsb_job;              /* 48 bytes */
+
+typedef struct lsb_plan lsb_plan;
+
+/* Create a plan for up to max_jobs jobs.  Allocates device and pinned host
+ * memory (this is the only allocating call of the batched form).  The plan
+ * owns a HIP graph {job-table upload, prologue kernel, persistent kernel}
+ * captured on the first run and reused afterwards. */
+int lsb_plan_create(lsb_plan **plan, int max_jobs);
+
+/* Replace the plan's job list (n_jobs <= max_jobs).  Validates every job on
+ * the host: a job with bad k or offsets is LSB_E_ARG for the whole call; an
+ * embed job whose len exceeds its capacity is not an error of the call: it
+ * gets status LSB_E_CAPACITY and no work.  Must not be called while a run of
+ * this plan is still in flight on a stream (the upload reads the host copy). */
+int lsb_plan_set_jobs(lsb_plan *plan, const lsb_job *jobs, int n_jobs);
+
+/* Run every job of the plan on `stream`.  For job j: status_dev[j] <- LSB_OK
+ * or its error; for extract jobs len_dev[j] <- decoded length (len_dev may
+ * be NULL if the plan has no extract job).  Results are identical to one
+ * lsb_embed / lsb_extract call per job. */
+int lsb_plan_run(lsb_plan *plan, const uint8_t *cover_arena,
+                 uint8_t *stego_arena, uint8_t *msg_arena, uint32_t *len_dev,
+                 int32_t *status_dev, void *stream);
+
+/* Total tiles (work units) of the current job list, for reporting. */
+int64_t lsb_plan_tiles(const lsb_plan *plan);
+
+void lsb_plan_destroy(lsb_plan *plan);
+
+/* ------------------------------------------------------------------------
+ * Launch configuration (autotuning).  A configuration is chosen per
+ * (op, k, size bucket); size bucket b covers n in [2^b, 2^(b+1)).  The
+ * library starts with built-in defaults; lsb_tune_set overrides an entry
+ * (the Python package loads its tuned table through it), lsb_autotune times
+ * every candidate on caller-provided device buffers and installs the best.
+ */
+typedef struct lsb_launch_cfg {
+    int32_t block;          /* threads per block: 64..1024, multiple of 64 */
+    int32_t unroll;         /* 16-byte vectors per lane per step: 1, 2, 4  */
+    int32_t blocks_per_cu;  /* grid cap = blocks_per_cu * CUs; 0 = no cap  */
+    int32_t nontemporal;    /* 1 = streaming (non-temporal) loads/stores   */
+} lsb_launch_cfg;
+
+int lsb_tune_get(int op, int k, uint64_t n, lsb_launch_cfg *cfg);
+int lsb_tune_set(int op, int k, int bucket, const lsb_launch_cfg *cfg);
+
+/* Time every candidate configuration for (op, k, n) on the given buffers
+ * (cover/stego of n bytes, msg of lsb_capacity(n,k) bytes; contents are
+ * overwritten), `reps` launches each, install the fastest for n's bucket and
+ * return it in *best (and its mean kernel time in *best_us). */
+int lsb_autotune(int op, int k, uint64_t n, uint8_t *cover, uint8_t *stego,
+                 uint8_t *msg, int reps, lsb_launch_cfg *best,
+                 double *best_us, void *stream);
+
+/* Batched-kernel configuration: tile size in 16-byte vectors per tile, the
+ * kernel's block/unroll/nontemporal choice and its grid cap. */
+int lsb_batch_tune_get(lsb_launch_cfg *cfg, int64_t *tile_vectors);
+int lsb_batch_tune_set(const lsb_launch_cfg *cfg, int64_t tile_vectors);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *lsb_last_error(void);
+
+/* Library version string. */
+const char *lsb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSB_H */

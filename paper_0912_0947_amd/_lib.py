@@ -1,0 +1,112 @@
+"""ctypes binding of liblsb.so (argument marshalling only).
+
+Every entry point of ``include/lsb.h`` is declared here with its C types.
+Loading fails loudly if the library has not been built: there is no CPU
+fallback for any operation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblsb.so")
+
+OK = 0
+E_ARG = -1
+E_CAPACITY = -2
+E_HEADER = -3
+E_BUFFER = -4
+E_HIP = -5
+E_NOMEM = -6
+OP_EMBED = 0
+OP_EXTRACT = 1
+
+ERROR_NAMES = {
+    OK: "LSB_OK", E_ARG: "LSB_E_ARG", E_CAPACITY: "LSB_E_CAPACITY", E_HEADER: "LSB_E_HEADER",
+    E_BUFFER: "LSB_E_BUFFER", E_HIP: "LSB_E_HIP", E_NOMEM: "LSB_E_NOMEM",
+}
+
+
+class LaunchCfg(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("unroll", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("nontemporal", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("cover_off", ctypes.c_uint64), ("stego_off", ctypes.c_uint64),
+                ("msg_off", ctypes.c_uint64), ("n", ctypes.c_uint64),
+                ("msg_cap", ctypes.c_uint64), ("len", ctypes.c_uint32),
+                ("k", ctypes.c_uint8), ("op", ctypes.c_uint8), ("reserved", ctypes.c_uint16)]
+
+
+assert ctypes.sizeof(Job) == 48
+
+_P = ctypes.c_void_p
+_U64 = ctypes.c_uint64
+_I64 = ctypes.c_int64
+_U32 = ctypes.c_uint32
+_I = ctypes.c_int
+
+SIGNATURES = {
+    "lsb_capacity": (_I64, [_U64, _I]),
+    "lsb_embed": (_I, [_P, _P, _U64, _P, _U32, _I, _P]),
+    "lsb_extract": (_I, [_P, _U64, _I, _P, _U64, _P, _P, _P]),
+    "lsb_extract_sync": (_I, [_P, _U64, _I, _P, _U64, ctypes.POINTER(_U32), _P]),
+    "lsb_embed_raw": (_I, [_P, _P, _U64, _U64, _P, _U64, _I, _P]),
+    "lsb_extract_raw": (_I, [_P, _U64, _U64, _P, _U64, _I, _P]),
+    "lsb_plan_create": (_I, [ctypes.POINTER(_P), _I]),
+    "lsb_plan_set_jobs": (_I, [_P, ctypes.POINTER(Job), _I]),
+    "lsb_plan_run": (_I, [_P, _P, _P, _P, _P, _P, _P]),
+    "lsb_plan_tiles": (_I64, [_P]),
+    "lsb_plan_destroy": (None, [_P]),
+    "lsb_tune_get": (_I, [_I, _I, _U64, ctypes.POINTER(LaunchCfg)]),
+    "lsb_tune_set": (_I, [_I, _I, _I, ctypes.POINTER(LaunchCfg)]),
+    "lsb_autotune": (_I, [_I, _I, _U64, _P, _P, _P, _I, ctypes.POINTER(LaunchCfg),
+                          ctypes.POINTER(ctypes.c_double), _P]),
+    "lsb_batch_tune_get": (_I, [ctypes.POINTER(LaunchCfg), ctypes.POINTER(_I64)]),
+    "lsb_batch_tune_set": (_I, [ctypes.POINTER(LaunchCfg), _I64]),
+    "lsb_last_error": (ctypes.c_char_p, []),
+    "lsb_version": (ctypes.c_char_p, []),
+}
+
+_lock = threading.Lock()
+_lib = None
+
+
+class LsbError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        self.code = code
+        super().__init__("%s (%d): %s" % (ERROR_NAMES.get(code, "?"), code, message))
+
+
+def lib():
+    """The loaded liblsb.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        with _lock:
+            if _lib is None:
+                if not os.path.exists(LIB_PATH):
+                    raise RuntimeError(
+                        "liblsb.so is not built (%s); run `python -m paper_0912_0947_amd.build` "
+                        "or __graft_entry__.build() -- there is no CPU fallback" % LIB_PATH)
+                handle = ctypes.CDLL(LIB_PATH)
+                for name, (res, args) in SIGNATURES.items():
+                    fn = getattr(handle, name)
+                    fn.restype = res
+                    fn.argtypes = args
+                from . import tune
+                tune.load(handle)  # stored launch configurations, if any
+                _lib = handle
+    return _lib
+
+
+def check(rc: int) -> int:
+    """Raise LsbError for a negative return code."""
+    if rc < 0:
+        raise LsbError(rc, lib().lsb_last_error().decode(errors="replace"))
+    return rc

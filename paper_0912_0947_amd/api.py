@@ -1,0 +1,128 @@
+"""Python API over liblsb.so for torch uint8 device tensors.
+
+Thin marshalling only: every operation runs in the HIP kernels of liblsb.so
+on the tensor's device and the caller's (or torch's current) stream.  Names
+follow include/lsb.h.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import (E_ARG, OK, OP_EMBED, OP_EXTRACT, LaunchCfg, LsbError, check, lib)
+
+__all__ = ["capacity", "embed", "extract", "extract_sync", "embed_raw", "extract_raw",
+           "tune_get", "tune_set", "autotune", "LsbError", "OK", "OP_EMBED", "OP_EXTRACT"]
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _u8(t: torch.Tensor, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8:
+        raise TypeError("%s must be a torch.uint8 tensor" % name)
+    if not t.is_cuda:
+        raise TypeError("%s must live on a GPU (no CPU path exists)" % name)
+    if not t.is_contiguous():
+        raise TypeError("%s must be contiguous" % name)
+    return t.data_ptr() if t.numel() else 0
+
+
+def capacity(n: int, k: int) -> int:
+    """Message capacity in bytes of an n-byte cover at k bits per byte."""
+    return check(lib().lsb_capacity(n, k))
+
+
+def embed(cover: torch.Tensor, msg: torch.Tensor, k: int, out: torch.Tensor | None = None,
+          stream=None) -> torch.Tensor:
+    """stego = cover with BE32(len(msg)) || msg in its low k bits.  ``out`` may
+    be ``cover`` itself (in place)."""
+    stego = torch.empty_like(cover) if out is None else out
+    if stego.numel() != cover.numel():
+        raise ValueError("out must have as many bytes as cover")
+    check(lib().lsb_embed(_u8(cover, "cover"), _u8(stego, "out"), cover.numel(), _u8(msg, "msg"),
+                          msg.numel(), k, _stream_ptr(stream)))
+    return stego
+
+
+def extract(stego: torch.Tensor, k: int, out: torch.Tensor | None = None,
+            len_status: torch.Tensor | None = None, stream=None):
+    """Asynchronous extract.  Returns (out, len_status): ``out`` holds the
+    message bytes, ``len_status`` an int32 device tensor [decoded length,
+    status] that is valid once the stream gets there."""
+    if out is None:
+        cap = lib().lsb_capacity(stego.numel(), k)
+        out = torch.empty(max(int(cap), 0), dtype=torch.uint8, device=stego.device)
+    if len_status is None:
+        len_status = torch.empty(2, dtype=torch.int32, device=stego.device)
+    if len_status.dtype != torch.int32 or len_status.numel() < 2 or not len_status.is_cuda:
+        raise TypeError("len_status must be an int32 device tensor of 2 elements")
+    base = len_status.data_ptr()
+    check(lib().lsb_extract(_u8(stego, "stego"), stego.numel(), k,
+                            _u8(out, "out") if out.numel() else None, out.numel(),
+                            ctypes.c_void_p(base), ctypes.c_void_p(base + 4), _stream_ptr(stream)))
+    return out, len_status
+
+
+def extract_sync(stego: torch.Tensor, k: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Extract and wait; returns the message as a view of ``out``.  Raises
+    LsbError for a header or buffer error."""
+    if out is None:
+        cap = lib().lsb_capacity(stego.numel(), k)
+        out = torch.empty(max(int(cap), 0), dtype=torch.uint8, device=stego.device)
+    ln = ctypes.c_uint32(0)
+    check(lib().lsb_extract_sync(_u8(stego, "stego"), stego.numel(), k,
+                                 _u8(out, "out") if out.numel() else None, out.numel(),
+                                 ctypes.byref(ln), _stream_ptr(stream)))
+    return out[: ln.value]
+
+
+def embed_raw(cover: torch.Tensor, t0: int, stream_bytes: torch.Tensor, stream_bits: int, k: int,
+              out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Embed logical-stream bits into cover bytes [t0, t0+n) of a longer
+    logical cover (no header)."""
+    stego = torch.empty_like(cover) if out is None else out
+    if stego.numel() != cover.numel():
+        raise ValueError("out must have as many bytes as cover")
+    check(lib().lsb_embed_raw(_u8(cover, "cover"), _u8(stego, "out"), cover.numel(), t0,
+                              _u8(stream_bytes, "stream_bytes"), stream_bits, k, _stream_ptr(stream)))
+    return stego
+
+
+def extract_raw(stego: torch.Tensor, t0: int, stream_out: torch.Tensor, stream_bits: int, k: int,
+                stream=None) -> torch.Tensor:
+    """Extract the stream bits carried by cover bytes [t0, t0+n) into the
+    logical-stream buffer ``stream_out``."""
+    check(lib().lsb_extract_raw(_u8(stego, "stego"), stego.numel(), t0, _u8(stream_out, "stream_out"),
+                                stream_bits, k, _stream_ptr(stream)))
+    return stream_out
+
+
+def tune_get(op: int, k: int, n: int) -> dict:
+    cfg = LaunchCfg()
+    check(lib().lsb_tune_get(op, k, n, ctypes.byref(cfg)))
+    return cfg.as_dict()
+
+
+def tune_set(op: int, k: int, bucket: int, block: int, unroll: int, blocks_per_cu: int, nontemporal: int):
+    cfg = LaunchCfg(block, unroll, blocks_per_cu, nontemporal)
+    check(lib().lsb_tune_set(op, k, bucket, ctypes.byref(cfg)))
+
+
+def autotune(op: int, k: int, cover: torch.Tensor, stego: torch.Tensor, msg: torch.Tensor,
+             reps: int = 10, stream=None):
+    """Time every launch configuration for (op, k, cover size) and install the
+    fastest.  Returns (config dict, mean kernel microseconds)."""
+    best = LaunchCfg()
+    us = ctypes.c_double(0.0)
+    check(lib().lsb_autotune(op, k, cover.numel(), _u8(cover, "cover"), _u8(stego, "stego"),
+                             _u8(msg, "msg"), reps, ctypes.byref(best), ctypes.byref(us),
+                             _stream_ptr(stream)))
+    return best.as_dict(), us.value
+
+
+_ = (E_ARG, LsbError)

@@ -1,0 +1,453 @@
+// lsb_batch.hip -- batched embed/extract over thousands of covers of uneven
+// size and k in one persistent launch, replayed through a HIP graph.
+//
+// The paper loops on the host over the rows of an image (Section VI steps
+// 4-5 split the data across rows; Section VII steps 3-4 likewise), paying a
+// copy and a launch per row.  Here every cover of a batch is a job, each job
+// is cut into tiles of T 16-byte vectors, and one persistent grid walks the
+// global tile list: block b takes tiles b, b + G, b + 2G, ...  A tile of job
+// j starts at field 16*T*t, so k*t0 is always a whole number of bytes and no
+// two tiles share an output byte.
+//
+// Graph of one run: {H2D copy of the job table from pinned host memory,
+// prologue kernel (per-job status; header decode for extract jobs),
+// persistent kernel}.  The graph is built once per plan; later runs only
+// update the copy size and kernel arguments in the executable graph.
+#include <string.h>
+
+#include <mutex>
+#include <new>
+
+#include "lsb_host.hpp"
+
+namespace lsb {
+
+struct PlanHeader {
+    uint64_t n_jobs;
+    uint64_t total_tiles;
+    uint64_t tile_vectors;
+    uint64_t reserved;
+};
+
+struct DevJob {
+    uint64_t cover_off, stego_off, msg_off, n, msg_cap;
+    uint64_t tile_begin;  // tiles of jobs before this one; entry n_jobs = total
+    uint32_t len;
+    uint8_t k, op;
+    int16_t status;  // host-validated status (embed); extract: decoded on device
+    uint64_t reserved;
+};
+static_assert(sizeof(DevJob) == 64, "DevJob is one 64-byte record");
+
+// Prologue: one wave per job writes the job's status (and decoded length).
+__global__ void __launch_bounds__(256)
+    lsb_batch_prologue(const PlanHeader *hdr, const DevJob *jobs, const uint8_t *stego_arena, uint32_t *len_dev,
+                       int32_t *status_dev) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t n_jobs = hdr->n_jobs;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t j = wave; j < n_jobs; j += n_waves) {
+        const DevJob J = jobs[j];
+        uint32_t len = J.len;
+        int status = J.status;
+        if (J.op == LSB_OP_EXTRACT && status == LSB_OK) {
+            len = 0;
+            status = LSB_E_HEADER;
+            if ((uint64_t)J.k * J.n >= 32) {
+                len = decode_header(stego_arena + J.stego_off, J.k, lane);
+                if (4 + (uint64_t)len > room_bytes(J.n, J.k)) status = LSB_E_HEADER;
+                else if ((uint64_t)len > J.msg_cap) status = LSB_E_BUFFER;
+                else status = LSB_OK;
+            }
+        }
+        if (lane == 0) {
+            if (len_dev) len_dev[j] = len;
+            status_dev[j] = status;
+        }
+    }
+}
+
+template <int UNR, bool NT>
+__device__ __forceinline__ void run_tile(const DevJob &J, uint64_t v_begin, uint64_t tile_vectors,
+                                         const uint8_t *cover_arena, uint8_t *stego_arena, uint8_t *msg_arena,
+                                         uint32_t len, uint32_t wave, uint32_t n_waves, uint32_t lane) {
+    Span s{};
+    s.n = J.n;
+    s.t0 = 0;
+    s.k = J.k;
+    s.hdr_len = 4;
+    s.words = 1;  // offsets are multiples of 256: stream side is dword aligned
+    if (J.op == LSB_OP_EMBED) {
+        s.src = cover_arena + J.cover_off;
+        s.dst = stego_arena + J.stego_off;
+        s.body = msg_arena + J.msg_off;
+        s.bits = 8 * (4 + (uint64_t)J.len);
+        s.hdr = J.len;
+        const Ranges r = embed_ranges(s);
+        uint64_t v_end = v_begin + tile_vectors;
+        if (v_end > r.count) v_end = r.count;
+        if (v_begin >= v_end) return;
+        switch (J.k) {
+            case 1: embed_walk<1, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+            case 2: embed_walk<2, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+            case 3: embed_walk<3, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+            case 4: embed_walk<4, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+            case 5: embed_walk<5, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+            case 6: embed_walk<6, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+            case 7: embed_walk<7, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+            default: embed_walk<8, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+        }
+    } else {
+        s.src = stego_arena + J.stego_off;
+        s.out = msg_arena + J.msg_off;
+        s.bits = 8 * (4 + (uint64_t)len);
+        const Ranges r = extract_ranges(s);
+        uint64_t v_end = v_begin + tile_vectors;
+        if (v_end > r.count) v_end = r.count;
+        if (v_begin >= v_end) return;
+        switch (J.k) {
+            case 1: extract_walk<1, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+            case 2: extract_walk<2, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+            case 3: extract_walk<3, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+            case 4: extract_walk<4, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+            case 5: extract_walk<5, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+            case 6: extract_walk<6, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+            case 7: extract_walk<7, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+            default: extract_walk<8, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+        }
+    }
+}
+
+// Persistent kernel.  Every wave of a block works on the block's tile; the
+// job of a tile is found by a forward search over the tile prefix that 64
+// lanes do in one step (jobs only move forward as the tile id grows).
+template <int UNR, bool NT>
+__global__ void __launch_bounds__(1024)
+    lsb_batch_kernel(const PlanHeader *hdr, const DevJob *jobs, const uint8_t *cover_arena, uint8_t *stego_arena,
+                     uint8_t *msg_arena, const uint32_t *len_dev, const int32_t *status_dev) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t n_waves = blockDim.x >> 6;
+    const uint64_t n_jobs = hdr->n_jobs;
+    const uint64_t total = hdr->total_tiles;
+    const uint64_t tile_vectors = hdr->tile_vectors;
+    uint64_t j = 0;
+    for (uint64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        // largest j with jobs[j].tile_begin <= tile (entry n_jobs holds total > tile)
+        for (;;) {
+            const uint64_t idx = j + 1 + lane;
+            const uint64_t tb = idx <= n_jobs ? jobs[idx].tile_begin : ~0ull;
+            const uint64_t below = __ballot(tb <= tile);
+            const uint32_t cnt = (uint32_t)__popcll(below);
+            j += cnt;
+            if (cnt < 64) break;
+        }
+        const DevJob J = jobs[j];
+        if (J.status != LSB_OK) continue;
+        uint32_t len = 0;
+        if (J.op == LSB_OP_EXTRACT) {
+            if (status_dev[j] != LSB_OK) continue;
+            len = len_dev[j];
+        }
+        const uint64_t v_begin = (tile - J.tile_begin) * tile_vectors;
+        run_tile<UNR, NT>(J, v_begin, tile_vectors, cover_arena, stego_arena, msg_arena, len, wave, n_waves, lane);
+    }
+}
+
+typedef void (*BatchFn)(const PlanHeader *, const DevJob *, const uint8_t *, uint8_t *, uint8_t *, const uint32_t *,
+                        const int32_t *);
+
+static BatchFn batch_fn(int unroll, int nt) {
+    if (unroll == 1) return nt ? lsb_batch_kernel<1, true> : lsb_batch_kernel<1, false>;
+    if (unroll == 2) return nt ? lsb_batch_kernel<2, true> : lsb_batch_kernel<2, false>;
+    return nt ? lsb_batch_kernel<4, true> : lsb_batch_kernel<4, false>;
+}
+
+// Batched-kernel configuration (global, read at each run).
+static std::mutex g_batch_mu;
+static lsb_launch_cfg g_batch_cfg = {256, 2, 8, 0};
+static int64_t g_tile_vectors = 8192;
+
+}  // namespace lsb
+
+using namespace lsb;
+
+struct lsb_plan {
+    int device = -1;
+    int max_jobs = 0;
+    int n_jobs = 0;
+    bool has_extract = false;
+    uint64_t total_tiles = 0;
+    size_t table_bytes = 0;  // bytes of header + (max_jobs + 1) records
+    size_t used_bytes = 0;   // bytes the next upload copies
+    uint8_t *host = nullptr;  // pinned mirror of the device table
+    uint8_t *dev = nullptr;
+    hipEvent_t done = nullptr;  // recorded after each run
+    bool ran = false;
+    // graph state
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t copy_node = nullptr, pro_node = nullptr, main_node = nullptr;
+    struct Args {
+        const PlanHeader *hdr;
+        const DevJob *jobs;
+        const uint8_t *cover;
+        uint8_t *stego;
+        uint8_t *msg;
+        uint32_t *len;
+        int32_t *status;
+    } args{};
+    lsb_launch_cfg cfg{};
+    int64_t tile_vectors = 0;
+    size_t graph_copy_bytes = 0;
+    unsigned main_grid = 0, pro_grid = 0;
+    BatchFn fn = nullptr;
+};
+
+static void destroy_graph(lsb_plan *p) {
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+static void fill_kernel_params(lsb_plan *p, void **argv, hipKernelNodeParams &kp, bool main) {
+    argv[0] = &p->args.hdr;
+    argv[1] = &p->args.jobs;
+    if (main) {
+        argv[2] = &p->args.cover;
+        argv[3] = &p->args.stego;
+        argv[4] = &p->args.msg;
+        argv[5] = &p->args.len;
+        argv[6] = &p->args.status;
+        kp.func = (void *)p->fn;
+        kp.gridDim = dim3(p->main_grid);
+        kp.blockDim = dim3(p->cfg.block);
+    } else {
+        argv[2] = &p->args.stego;
+        argv[3] = &p->args.len;
+        argv[4] = &p->args.status;
+        kp.func = (void *)lsb_batch_prologue;
+        kp.gridDim = dim3(p->pro_grid);
+        kp.blockDim = dim3(256);
+    }
+    kp.kernelParams = argv;
+    kp.extra = nullptr;
+    kp.sharedMemBytes = 0;
+}
+
+// Build (first run) or update the executable graph for the current state.
+static int prepare_graph(lsb_plan *p) {
+    void *main_argv[7], *pro_argv[5];
+    hipKernelNodeParams main_kp{}, pro_kp{};
+    fill_kernel_params(p, main_argv, main_kp, true);
+    fill_kernel_params(p, pro_argv, pro_kp, false);
+    hipError_t e;
+    if (!p->exec) {
+        e = hipGraphCreate(&p->graph, 0);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
+        e = hipGraphAddMemcpyNode1D(&p->copy_node, p->graph, nullptr, 0, p->dev, p->host, p->used_bytes,
+                                    hipMemcpyHostToDevice);
+        if (e != hipSuccess) return destroy_graph(p), hip_fail(e, "hipGraphAddMemcpyNode1D");
+        e = hipGraphAddKernelNode(&p->pro_node, p->graph, &p->copy_node, 1, &pro_kp);
+        if (e != hipSuccess) return destroy_graph(p), hip_fail(e, "hipGraphAddKernelNode(prologue)");
+        e = hipGraphAddKernelNode(&p->main_node, p->graph, &p->pro_node, 1, &main_kp);
+        if (e != hipSuccess) return destroy_graph(p), hip_fail(e, "hipGraphAddKernelNode(persistent)");
+        e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return destroy_graph(p), hip_fail(e, "hipGraphInstantiate");
+        p->graph_copy_bytes = p->used_bytes;
+        return LSB_OK;
+    }
+    if (p->graph_copy_bytes != p->used_bytes) {
+        e = hipGraphExecMemcpyNodeSetParams1D(p->exec, p->copy_node, p->dev, p->host, p->used_bytes,
+                                              hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphExecMemcpyNodeSetParams1D");
+        p->graph_copy_bytes = p->used_bytes;
+    }
+    e = hipGraphExecKernelNodeSetParams(p->exec, p->pro_node, &pro_kp);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphExecKernelNodeSetParams(prologue)");
+    e = hipGraphExecKernelNodeSetParams(p->exec, p->main_node, &main_kp);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphExecKernelNodeSetParams(persistent)");
+    return LSB_OK;
+}
+
+extern "C" {
+
+int lsb_plan_create(lsb_plan **out, int max_jobs) {
+    clear_error();
+    if (!out) return fail(LSB_E_ARG, "lsb_plan_create: null plan pointer");
+    *out = nullptr;
+    if (max_jobs < 1 || max_jobs > (1 << 24)) return fail(LSB_E_ARG, "lsb_plan_create: max_jobs=%d", max_jobs);
+    lsb_plan *p = new (std::nothrow) lsb_plan();
+    if (!p) return fail(LSB_E_NOMEM, "lsb_plan_create: out of host memory");
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) return delete p, hip_fail(e, "hipGetDevice");
+    p->max_jobs = max_jobs;
+    p->table_bytes = sizeof(PlanHeader) + sizeof(DevJob) * ((size_t)max_jobs + 1);
+    e = hipHostMalloc((void **)&p->host, p->table_bytes, hipHostMallocDefault);
+    if (e != hipSuccess) return delete p, fail(LSB_E_NOMEM, "lsb_plan_create: hipHostMalloc failed");
+    e = hipMalloc((void **)&p->dev, p->table_bytes);
+    if (e != hipSuccess) return hipHostFree(p->host), delete p, fail(LSB_E_NOMEM, "lsb_plan_create: hipMalloc failed");
+    e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+    if (e != hipSuccess) return hipFree(p->dev), hipHostFree(p->host), delete p, hip_fail(e, "hipEventCreate");
+    memset(p->host, 0, p->table_bytes);
+    p->used_bytes = sizeof(PlanHeader) + sizeof(DevJob);
+    *out = p;
+    return LSB_OK;
+}
+
+int lsb_plan_set_jobs(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
+    clear_error();
+    if (!p) return fail(LSB_E_ARG, "lsb_plan_set_jobs: null plan");
+    if (n_jobs < 0 || n_jobs > p->max_jobs)
+        return fail(LSB_E_ARG, "lsb_plan_set_jobs: n_jobs=%d outside 0..%d", n_jobs, p->max_jobs);
+    if (n_jobs && !jobs) return fail(LSB_E_ARG, "lsb_plan_set_jobs: null job list");
+    int64_t tv;
+    {
+        std::lock_guard<std::mutex> g(g_batch_mu);
+        tv = g_tile_vectors;
+    }
+    // validate everything before touching the mirror
+    for (int i = 0; i < n_jobs; ++i) {
+        const lsb_job &J = jobs[i];
+        if (J.k < 1 || J.k > 8) return fail(LSB_E_ARG, "job %d: k=%d outside 1..8", i, (int)J.k);
+        if (J.op != LSB_OP_EMBED && J.op != LSB_OP_EXTRACT) return fail(LSB_E_ARG, "job %d: bad op %d", i, (int)J.op);
+        if ((J.cover_off | J.stego_off | J.msg_off) & 255)
+            return fail(LSB_E_ARG, "job %d: arena offsets must be multiples of 256", i);
+        if (J.n > (1ull << 48)) return fail(LSB_E_ARG, "job %d: n out of range", i);
+        if (J.reserved) return fail(LSB_E_ARG, "job %d: reserved field must be 0", i);
+    }
+    // the previous run's upload must have read the mirror before it changes
+    if (p->ran) {
+        hipError_t e = hipEventSynchronize(p->done);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(plan)");
+    }
+    PlanHeader *h = (PlanHeader *)p->host;
+    DevJob *d = (DevJob *)(p->host + sizeof(PlanHeader));
+    uint64_t tiles = 0;
+    bool has_extract = false;
+    for (int i = 0; i < n_jobs; ++i) {
+        const lsb_job &J = jobs[i];
+        DevJob &D = d[i];
+        memset(&D, 0, sizeof D);
+        D.cover_off = J.cover_off;
+        D.stego_off = J.stego_off;
+        D.msg_off = J.msg_off;
+        D.n = J.n;
+        D.msg_cap = J.msg_cap;
+        D.len = J.len;
+        D.k = J.k;
+        D.op = J.op;
+        D.tile_begin = tiles;
+        D.status = LSB_OK;
+        uint64_t vectors = ceil_div(J.n, 16);
+        if (J.op == LSB_OP_EMBED) {
+            const uint64_t room = room_bytes(J.n, J.k);
+            if (room < 4 || (uint64_t)J.len > room - 4) {
+                D.status = LSB_E_CAPACITY;
+                vectors = 0;
+            }
+        } else {
+            has_extract = true;
+            // worst case: the stream may fill the cover or the output buffer
+            const uint64_t room = room_bytes(J.n, J.k);
+            const uint64_t cap = room >= 4 ? room - 4 : 0;
+            const uint64_t max_len = J.msg_cap < cap ? J.msg_cap : cap;
+            const uint64_t v_stream = ceil_div(4 + max_len, 2 * (uint64_t)J.k);
+            if (v_stream < vectors) vectors = v_stream;
+            if ((uint64_t)J.k * J.n < 32) vectors = 0;
+        }
+        tiles += ceil_div(vectors, (uint64_t)tv);
+    }
+    DevJob &S = d[n_jobs];  // sentinel
+    memset(&S, 0, sizeof S);
+    S.tile_begin = tiles;
+    h->n_jobs = (uint64_t)n_jobs;
+    h->total_tiles = tiles;
+    h->tile_vectors = (uint64_t)tv;
+    p->n_jobs = n_jobs;
+    p->total_tiles = tiles;
+    p->has_extract = has_extract;
+    p->tile_vectors = tv;
+    p->used_bytes = sizeof(PlanHeader) + sizeof(DevJob) * ((size_t)n_jobs + 1);
+    return LSB_OK;
+}
+
+int64_t lsb_plan_tiles(const lsb_plan *p) { return p ? (int64_t)p->total_tiles : fail(LSB_E_ARG, "null plan"); }
+
+int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, uint8_t *msg_arena, uint32_t *len_dev,
+                 int32_t *status_dev, void *stream) {
+    clear_error();
+    if (!p) return fail(LSB_E_ARG, "lsb_plan_run: null plan");
+    if (p->n_jobs == 0) return LSB_OK;
+    if (!status_dev) return fail(LSB_E_ARG, "lsb_plan_run: null status_dev");
+    if (p->has_extract && !len_dev) return fail(LSB_E_ARG, "lsb_plan_run: extract jobs need len_dev");
+    if (!stego_arena || !msg_arena) return fail(LSB_E_ARG, "lsb_plan_run: null arena");
+    if (((uintptr_t)cover_arena | (uintptr_t)stego_arena | (uintptr_t)msg_arena) & 255)
+        return fail(LSB_E_ARG, "lsb_plan_run: arena base pointers must be 256-byte aligned");
+    int dev = -1;
+    hipGetDevice(&dev);
+    if (dev != p->device) return fail(LSB_E_ARG, "lsb_plan_run: plan belongs to device %d, current is %d", p->device, dev);
+    lsb_launch_cfg cfg;
+    int64_t tv;
+    {
+        std::lock_guard<std::mutex> g(g_batch_mu);
+        cfg = g_batch_cfg;
+        tv = g_tile_vectors;
+    }
+    if (tv != p->tile_vectors) return fail(LSB_E_ARG, "lsb_plan_run: tile size changed since lsb_plan_set_jobs");
+    const bool rebuild = p->exec && (cfg.block != p->cfg.block || cfg.unroll != p->cfg.unroll ||
+                                     cfg.nontemporal != p->cfg.nontemporal);
+    if (rebuild) destroy_graph(p);
+    p->cfg = cfg;
+    p->fn = batch_fn(cfg.unroll, cfg.nontemporal);
+    const uint64_t cap_blocks = (uint64_t)(cfg.blocks_per_cu > 0 ? cfg.blocks_per_cu : 8) * (uint64_t)device_cus();
+    p->main_grid = (unsigned)(p->total_tiles < cap_blocks ? (p->total_tiles ? p->total_tiles : 1) : cap_blocks);
+    p->pro_grid = (unsigned)ceil_div((uint64_t)p->n_jobs, 4);  // 4 waves per block, one job per wave
+    if (p->pro_grid > 4096) p->pro_grid = 4096;
+    p->args.hdr = (const PlanHeader *)p->dev;
+    p->args.jobs = (const DevJob *)(p->dev + sizeof(PlanHeader));
+    p->args.cover = cover_arena;
+    p->args.stego = stego_arena;
+    p->args.msg = msg_arena;
+    p->args.len = len_dev;
+    p->args.status = status_dev;
+    int rc = prepare_graph(p);
+    if (rc != LSB_OK) return rc;
+    hipError_t e = hipGraphLaunch(p->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    e = hipEventRecord(p->done, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord(plan)");
+    p->ran = true;
+    return LSB_OK;
+}
+
+void lsb_plan_destroy(lsb_plan *p) {
+    if (!p) return;
+    if (p->ran) hipEventSynchronize(p->done);
+    destroy_graph(p);
+    if (p->done) hipEventDestroy(p->done);
+    if (p->dev) hipFree(p->dev);
+    if (p->host) hipHostFree(p->host);
+    delete p;
+}
+
+int lsb_batch_tune_get(lsb_launch_cfg *cfg, int64_t *tile_vectors) {
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    if (cfg) *cfg = g_batch_cfg;
+    if (tile_vectors) *tile_vectors = g_tile_vectors;
+    return LSB_OK;
+}
+
+int lsb_batch_tune_set(const lsb_launch_cfg *cfg, int64_t tile_vectors) {
+    if (!cfg || !cfg_valid(*cfg)) return fail(LSB_E_ARG, "lsb_batch_tune_set: invalid configuration");
+    if (tile_vectors < 64 || tile_vectors > (1ll << 30) || tile_vectors % 64)
+        return fail(LSB_E_ARG, "lsb_batch_tune_set: tile_vectors must be a multiple of 64 in [64, 2^30]");
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    g_batch_cfg = *cfg;
+    g_tile_vectors = tile_vectors;
+    return LSB_OK;
+}
+
+}  // extern "C"

@@ -49,14 +49,17 @@ def smooth_cover(height: int, width: int, channels: int = 3,
     phi = p.uniform(0.0, 2.0 * math.pi, size=channels)
     noise = rng(noise_seed)
     out = np.empty((height, width, channels), dtype=np.uint8)
-    x = np.arange(width, dtype=np.float64) / width
+    x = (np.arange(width, dtype=np.float64) / width)[None, :]
     for y0 in range(0, height, rows_per_chunk):
         y1 = min(height, y0 + rows_per_chunk)
         y = (np.arange(y0, y1, dtype=np.float64) / height)[:, None]
         for c in range(channels):
-            v = 128.0 + amplitude * np.sin(2.0 * math.pi * (a[c] * x[None, :] + b[c] * y) + phi[c])
-            v += noise.normal(0.0, sigma, size=v.shape)
-            np.clip(np.rint(v), 0, 255, out=v)
+            phase = (2.0 * math.pi * (a[c] * x + b[c] * y) + phi[c]).astype(np.float32)
+            v = np.sin(phase, out=phase)
+            v *= np.float32(amplitude)
+            v += np.float32(128.0)
+            v += noise.standard_normal(size=v.shape, dtype=np.float32) * np.float32(sigma)
+            np.clip(np.rint(v, out=v), 0, 255, out=v)
             out[y0:y1, :, c] = v.astype(np.uint8)
     return out
 

@@ -1,0 +1,153 @@
+"""Autotuning driver: runs lsb_autotune over (op, k, size) points and the
+batched-kernel sweep, and stores the winners as JSON next to this file.
+
+``load()`` installs a stored table into the library (called on import of
+paper_0912_0947_amd.api).  Buckets that were not tuned take the entry of the
+nearest tuned bucket of the same (op, k).
+
+Usage on a GPU: ``python -m paper_0912_0947_amd.tune [--batch]``.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(HERE, "tune_gfx950.json")
+SIZES = [1 << 12, 1 << 14, 1 << 16, 1 << 18, 786432, 1 << 21, 6220800, 1 << 24, 1 << 26, 201326592, 1 << 29]
+KS = range(1, 9)
+
+
+def bucket(n: int) -> int:
+    return max(int(n).bit_length() - 1, 0)
+
+
+def load(handle=None, path: str = TABLE) -> bool:
+    """Install a stored tuning table into the library; returns False if there
+    is none.  ``handle`` is the loaded liblsb.so (the binding passes it while
+    it loads the library)."""
+    if not os.path.exists(path):
+        return False
+    import ctypes
+
+    from ._lib import LaunchCfg, check
+
+    if handle is None:
+        from ._lib import lib
+        handle = lib()
+    with open(path) as f:
+        table = json.load(f)
+    by_opk = {}
+    for e in table.get("entries", []):
+        by_opk.setdefault((e["op"], e["k"]), []).append(e)
+    for (op, k), entries in by_opk.items():
+        tuned = {e["bucket"]: e["cfg"] for e in entries}
+        keys = sorted(tuned)
+        for b in range(64):
+            c = tuned[min(keys, key=lambda t: (abs(t - b), t))]
+            cfg = LaunchCfg(c["block"], c["unroll"], c["blocks_per_cu"], c["nontemporal"])
+            if handle.lsb_tune_set(op, k, b, ctypes.byref(cfg)) != 0:
+                raise RuntimeError("bad tuning entry %s" % c)
+    if "batch" in table:
+        c = table["batch"]["cfg"]
+        cfg = LaunchCfg(c["block"], c["unroll"], c["blocks_per_cu"], c["nontemporal"])
+        if handle.lsb_batch_tune_set(ctypes.byref(cfg), int(table["batch"]["tile_vectors"])) != 0:
+            raise RuntimeError("bad batch tuning entry %s" % table["batch"])
+    _ = check
+    return True
+
+
+def tune_plain(reps: int = 5, sizes=SIZES, ks=KS, log=print):
+    import torch
+
+    from . import api, inputs
+
+    dev = torch.device("cuda:0")
+    entries = []
+    biggest = max(sizes)
+    cover = torch.empty(biggest, dtype=torch.uint8, device=dev)
+    stego = torch.empty(biggest, dtype=torch.uint8, device=dev)
+    msg = torch.empty(biggest, dtype=torch.uint8, device=dev)
+    inputs.fill_uniform(cover, 11)
+    inputs.fill_uniform(msg, 12)
+    for n in sizes:
+        for k in ks:
+            cap = api.capacity(n, k)
+            for op in (api.OP_EMBED, api.OP_EXTRACT):
+                cfg, us = api.autotune(op, k, cover[:n], stego[:n], msg[:cap], reps=reps)
+                entries.append({"op": op, "k": k, "bucket": bucket(n), "n": n, "cfg": cfg, "us": round(us, 2)})
+                log("op=%d k=%d n=%d -> %s %.1f us" % (op, k, n, cfg, us))
+    return entries
+
+
+def tune_batch(log=print, count: int = 4096):
+    """Sweep the batched kernel's configuration on the uneven 4096-cover
+    workload (embed then extract per candidate)."""
+    import torch
+
+    from . import api, batch
+    from .workloads import BatchWorkload
+
+    dev = torch.device("cuda:0")
+    wl = BatchWorkload(count, api.capacity, seed=401)
+    cover, stego, msg, out = wl.allocate(dev)
+    status = torch.zeros(count, dtype=torch.int32, device=dev)
+    lens = torch.zeros(count, dtype=torch.int32, device=dev)
+    best = None
+    results = []
+    for tv in (4096, 16384, 65536):
+        for block in (256, 512):
+            for unroll in (2, 4):
+                for bpc in (4, 8, 16):
+                    for nt in (0, 1):
+                        batch.tune_set(block, unroll, bpc, nt, tv)
+                        pe, px = batch.Plan(count), batch.Plan(count)
+                        pe.set_jobs(wl.jobs(api.OP_EMBED))
+                        px.set_jobs(wl.jobs(api.OP_EXTRACT))
+                        times = []
+                        for rep in range(3):
+                            torch.cuda.synchronize()
+                            t0 = time.perf_counter()
+                            pe.run(cover, stego, msg, lens, status)
+                            px.run(None, stego, out, lens, status)
+                            torch.cuda.synchronize()
+                            times.append(time.perf_counter() - t0)
+                        pe.close()
+                        px.close()
+                        t = min(times[1:])
+                        cfg = {"block": block, "unroll": unroll, "blocks_per_cu": bpc, "nontemporal": nt}
+                        results.append({"cfg": cfg, "tile_vectors": tv, "ms": round(t * 1e3, 3)})
+                        log("batch %s tv=%d -> %.3f ms" % (cfg, tv, t * 1e3))
+                        if best is None or t < best[0]:
+                            best = (t, cfg, tv)
+    return {"cfg": best[1], "tile_vectors": best[2], "ms": round(best[0] * 1e3, 3)}, results
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--batch", action="store_true", help="also sweep the batched kernel")
+    ap.add_argument("--out", default=TABLE)
+    args = ap.parse_args()
+    import torch
+
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    table = {"arch": "gfx950", "device": torch.cuda.get_device_name(0), "created": time.strftime("%Y-%m-%d %H:%M"),
+             "entries": tune_plain(args.reps, log=log)}
+    if args.batch:
+        table["batch"], table["batch_sweep"] = tune_batch(log=log)
+    elif os.path.exists(args.out):
+        with open(args.out) as f:
+            old = json.load(f)
+        if "batch" in old:
+            table["batch"] = old["batch"]
+    with open(args.out, "w") as f:
+        json.dump(table, f, indent=1)
+    log("wrote", args.out)
+
+
+if __name__ == "__main__":
+    main()

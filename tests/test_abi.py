@@ -1,0 +1,80 @@
+"""The C ABI library builds, loads without a GPU and exports every function
+that include/lsb.h declares.  Only host-side calls are made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lsb.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|int64_t|void|char)\s*\*?\s*(lsb_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_0912_0947_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_0912_0947_amd import build
+        build.build()
+    return _lib.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["lsb_capacity", "lsb_embed", "lsb_extract", "lsb_extract_sync", "lsb_embed_raw",
+                 "lsb_extract_raw", "lsb_plan_create", "lsb_plan_set_jobs", "lsb_plan_run",
+                 "lsb_plan_destroy", "lsb_last_error", "lsb_autotune", "lsb_tune_set", "lsb_tune_get"]:
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, "declared in lsb.h but not exported: %s" % missing
+
+
+def test_binding_covers_the_header():
+    from paper_0912_0947_amd import _lib
+    assert sorted(_lib.SIGNATURES) == declared_functions()
+
+
+def test_capacity_is_host_only(lib):
+    import oracle
+    for k in range(1, 9):
+        for n in [0, 3, 31, 32, 33, 1000, 786432, 201326592, 3732480000]:
+            assert lib.lsb_capacity(n, k) == oracle.capacity(n, k)
+    assert lib.lsb_capacity(100, 0) == -1
+    assert b"outside" in lib.lsb_last_error()
+
+
+def test_tune_table_roundtrip(lib):
+    from paper_0912_0947_amd._lib import LaunchCfg
+    cfg = LaunchCfg()
+    assert lib.lsb_tune_get(0, 1, 1 << 27, ctypes.byref(cfg)) == 0
+    old = LaunchCfg(cfg.block, cfg.unroll, cfg.blocks_per_cu, cfg.nontemporal)
+    new = LaunchCfg(512, 4, 2, 1)
+    assert lib.lsb_tune_set(0, 1, 27, ctypes.byref(new)) == 0
+    got = LaunchCfg()
+    lib.lsb_tune_get(0, 1, (1 << 27) + 5, ctypes.byref(got))
+    assert got.as_dict() == new.as_dict()
+    lib.lsb_tune_get(0, 1, 1 << 26, ctypes.byref(got))
+    assert got.as_dict() == old.as_dict()  # other buckets untouched
+    assert lib.lsb_tune_set(0, 1, 27, ctypes.byref(old)) == 0
+    bad = LaunchCfg(100, 3, 0, 0)
+    assert lib.lsb_tune_set(0, 1, 27, ctypes.byref(bad)) == -1
+
+
+def test_no_cpu_fallback(monkeypatch, tmp_path):
+    """Without the built library every operation raises instead of running
+    anywhere else."""
+    from paper_0912_0947_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        _lib.lib()

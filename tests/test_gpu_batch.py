@@ -1,0 +1,227 @@
+"""GPU parity of the batched (persistent, graph-replayed) path.
+
+Each job's result must equal the oracle's and the single-call result, for
+mixed embed/extract batches with invalid jobs, tiny tiles (many tile
+boundaries), shuffled job orders and plan reuse."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_0912_0947_amd import api, batch, inputs
+from paper_0912_0947_amd._lib import E_BUFFER, E_CAPACITY, E_HEADER, OK, OP_EMBED, OP_EXTRACT
+from paper_0912_0947_amd.workloads import BatchWorkload
+
+from gpu_helpers import DEV, assert_bytes_equal, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _mixed_batch(count, seed):
+    """Host-side batch: per job (n, k, op, cover, payload, stego input,
+    expected status/len/outputs) from the oracle."""
+    g = inputs.rng(seed)
+    jobs = []
+    for i in range(count):
+        kind = g.integers(0, 10)
+        if kind < 3:
+            n = int(g.integers(1, 300))
+        elif kind < 8:
+            n = int(g.integers(300, 200_000))
+        else:
+            n = int(g.integers(200_000, 3_000_000))
+        k = int(g.integers(1, 9))
+        op = OP_EMBED if g.integers(0, 2) == 0 else OP_EXTRACT
+        cover = inputs.random_bytes(n, seed, i, 1)
+        cap = oracle.capacity(n, k)
+        job = {"n": n, "k": k, "op": op, "cover": cover}
+        if op == OP_EMBED:
+            if cap < 0:
+                ln = 0
+            else:
+                ln = int(g.integers(0, cap + 1)) if g.integers(0, 8) else cap + 1  # some overflow
+            msg = inputs.random_bytes(ln, seed, i, 2)
+            rc, want = oracle.embed(cover, msg, k)
+            job.update(msg=msg, len=ln, status=rc if rc < 0 else OK, want=want if rc == 0 else None)
+        else:
+            flavour = g.integers(0, 6)
+            if cap < 0:
+                stego = cover
+                out_cap = 8
+            else:
+                ln = int(g.integers(0, cap + 1))
+                msg = inputs.random_bytes(ln, seed, i, 3)
+                rc, stego = oracle.embed(cover, msg, k)
+                out_cap = ln
+                if flavour == 0 and n * k >= 32:  # corrupt header: claim cap + 1
+                    hdr = np.frombuffer(int(cap + 1).to_bytes(4, "big"), np.uint8)
+                    rc, stego = oracle.embed_raw(stego, 0, hdr, 32, k)
+                elif flavour == 1 and ln > 0:
+                    out_cap = ln - 1  # output buffer one byte short
+            orc, oln, omsg = oracle.extract(stego, k, out_cap=out_cap)
+            job.update(stego=stego, msg_cap=out_cap, status=orc, len=oln, want=omsg)
+        jobs.append(job)
+    return jobs
+
+
+def _layout(jobs):
+    off_c = off_m = 0
+    table = batch.make_jobs(len(jobs))
+    for i, j in enumerate(jobs):
+        table[i]["cover_off"] = table[i]["stego_off"] = off_c
+        off_c = batch.align_up(off_c + j["n"])
+        table[i]["msg_off"] = off_m
+        size = j["len"] if j["op"] == OP_EMBED else j["msg_cap"]
+        off_m = batch.align_up(off_m + max(size, 1))
+        table[i]["n"] = j["n"]
+        table[i]["k"] = j["k"]
+        table[i]["op"] = j["op"]
+        if j["op"] == OP_EMBED:
+            table[i]["len"] = j["len"]
+        else:
+            table[i]["msg_cap"] = j["msg_cap"]
+    return table, off_c, off_m
+
+
+def _run_and_check(jobs, order=None, tile_vectors=None, plan=None):
+    table, cbytes, mbytes = _layout(jobs)
+    cover_h = np.zeros(max(cbytes, 1), np.uint8)
+    stego_h = np.zeros(max(cbytes, 1), np.uint8)
+    msg_h = np.zeros(max(mbytes, 1), np.uint8)
+    for t, j in zip(table, jobs):
+        c0 = int(t["cover_off"])
+        if j["op"] == OP_EMBED:
+            cover_h[c0:c0 + j["n"]] = j["cover"]
+            m0 = int(t["msg_off"])
+            msg_h[m0:m0 + j["len"]] = j["msg"][:j["len"]]
+        else:
+            stego_h[c0:c0 + j["n"]] = j["stego"]
+    cover = torch.from_numpy(cover_h).to(DEV)
+    stego = torch.from_numpy(stego_h).to(DEV)
+    msg = torch.from_numpy(msg_h).to(DEV)
+    status = torch.full((len(jobs),), 99, dtype=torch.int32, device=DEV)
+    lens = torch.zeros(len(jobs), dtype=torch.int32, device=DEV)
+    if tile_vectors is not None:
+        cfg, _ = batch.tune_get()
+        batch.tune_set(cfg["block"], cfg["unroll"], cfg["blocks_per_cu"], cfg["nontemporal"], tile_vectors)
+    own = plan is None
+    if own:
+        plan = batch.Plan(len(jobs))
+    idx = np.arange(len(jobs)) if order is None else order
+    try:
+        plan.set_jobs(table[idx])
+        plan.run(cover, stego, msg, lens, status)
+        torch.cuda.synchronize()
+    finally:
+        if own:
+            plan.close()
+    st = status.cpu().numpy()
+    ln = lens.cpu().numpy().astype(np.uint32)
+    stego_o = to_host(stego)
+    msg_o = to_host(msg)
+    for pos, i in enumerate(idx):
+        j, t = jobs[i], table[i]
+        tag = "job %d (n=%d k=%d op=%d)" % (i, j["n"], j["k"], j["op"])
+        assert st[pos] == j["status"], "%s: status %d, want %d" % (tag, st[pos], j["status"])
+        c0, m0 = int(t["cover_off"]), int(t["msg_off"])
+        if j["op"] == OP_EMBED:
+            if j["status"] == OK:
+                assert_bytes_equal(stego_o[c0:c0 + j["n"]], j["want"], tag)
+        else:
+            assert ln[pos] == j["len"], "%s: len %d want %d" % (tag, ln[pos], j["len"])
+            if j["status"] == OK:
+                assert_bytes_equal(msg_o[m0:m0 + j["len"]], j["want"], tag)
+    return plan
+
+
+@pytest.fixture(scope="module")
+def mixed():
+    return _mixed_batch(160, 901)
+
+
+def test_mixed_batch(mixed):
+    statuses = {j["status"] for j in mixed}
+    assert {OK, E_CAPACITY, E_HEADER, E_BUFFER} <= statuses, statuses
+    _run_and_check(mixed)
+
+
+def test_mixed_batch_shuffled(mixed):
+    order = inputs.rng(902).permutation(len(mixed))
+    _run_and_check(mixed, order=order)
+
+
+@pytest.mark.parametrize("tv", [64, 1024])
+def test_small_tiles(mixed, tv):
+    """Tiles of 64 or 1024 vectors put many tile boundaries inside each cover;
+    results must not change."""
+    old_cfg, old_tv = batch.tune_get()
+    try:
+        _run_and_check(mixed, tile_vectors=tv)
+    finally:
+        batch.tune_set(old_cfg["block"], old_cfg["unroll"], old_cfg["blocks_per_cu"], old_cfg["nontemporal"], old_tv)
+
+
+def test_plan_reuse_across_job_lists(mixed):
+    """One plan, several job lists and sizes: the executable graph is updated
+    in place and every run is correct."""
+    plan = batch.Plan(len(mixed))
+    try:
+        _run_and_check(mixed[:40], plan=plan)
+        _run_and_check(mixed, plan=plan)
+        _run_and_check(mixed[100:], plan=plan)
+    finally:
+        plan.close()
+
+
+def test_plan_errors():
+    plan = batch.Plan(4)
+    try:
+        j = batch.make_jobs(1)
+        j[0]["n"], j[0]["k"], j[0]["cover_off"] = 100, 2, 8  # offset not 256-aligned
+        with pytest.raises(Exception):
+            plan.set_jobs(j)
+        j[0]["cover_off"], j[0]["k"] = 0, 9
+        with pytest.raises(Exception):
+            plan.set_jobs(j)
+        with pytest.raises(Exception):
+            plan.set_jobs(batch.make_jobs(5))  # more than max_jobs
+    finally:
+        plan.close()
+
+
+def test_config4_full_scale():
+    """4096 uneven covers (W, H ~ U{64..4096}, 1 or 3 channels, k in {1, 2},
+    message 10-100 % of capacity; about 35 GB of covers): one batched embed and
+    one batched extract.  Every job is compared with a single-call embed on
+    the device and every message with its input; sampled jobs (smallest,
+    largest and random ones) are compared with the oracle."""
+    wl = BatchWorkload(4096, oracle.capacity, seed=401)
+    cover, stego, msg, out = wl.allocate(DEV)
+    status = torch.full((wl.count,), 99, dtype=torch.int32, device=DEV)
+    lens = torch.zeros(wl.count, dtype=torch.int32, device=DEV)
+    plan = batch.Plan(wl.count)
+    try:
+        plan.set_jobs(wl.jobs(OP_EMBED))
+        plan.run(cover, stego, msg, lens, status)
+        torch.cuda.synchronize()
+        assert bool((status == OK).all())
+        plan.set_jobs(wl.jobs(OP_EXTRACT))
+        status.fill_(99)
+        plan.run(None, stego, out, lens, status)
+        torch.cuda.synchronize()
+        assert bool((status == OK).all())
+        assert np.array_equal(lens.cpu().numpy().astype(np.int64), wl.len)
+    finally:
+        plan.close()
+    scratch = torch.empty(int(wl.n.max()), dtype=torch.uint8, device=DEV)
+    for i in range(wl.count):
+        c0, n, m0, ln, k = int(wl.cover_off[i]), int(wl.n[i]), int(wl.msg_off[i]), int(wl.len[i]), int(wl.k[i])
+        single = api.embed(cover[c0:c0 + n], msg[m0:m0 + ln], k, out=scratch[:n])
+        assert torch.equal(single, stego[c0:c0 + n]), "job %d differs from the single call" % i
+        assert torch.equal(out[m0:m0 + ln], msg[m0:m0 + ln]), "job %d message differs" % i
+    sample = {int(np.argmin(wl.n)), int(np.argmax(wl.n))} | set(inputs.rng(404).integers(0, wl.count, 4).tolist())
+    for i in sorted(sample):
+        c0, n, m0, ln, k = int(wl.cover_off[i]), int(wl.n[i]), int(wl.msg_off[i]), int(wl.len[i]), int(wl.k[i])
+        rc, want = oracle.embed(to_host(cover[c0:c0 + n]), to_host(msg[m0:m0 + ln]), k)
+        assert rc == 0
+        assert_bytes_equal(to_host(stego[c0:c0 + n]), want, "cfg4 job %d vs oracle" % i)
