@@ -68,6 +68,101 @@ def cpu_baseline(cover_np, msgs):
                       "buffers (%.1f s), single thread" % dt}
 
 
+def bench_batched(api, batch, dev, log_fn, reps=3):
+    """Uneven batch of 4096 covers (about 35 GB): one persistent graph launch
+    per op against a loop of one plain launch per cover on one stream."""
+    import ctypes
+
+    import torch
+
+    from paper_0912_0947_amd._lib import lib
+    from paper_0912_0947_amd.workloads import BatchWorkload
+
+    wl = BatchWorkload(4096, api.capacity, seed=401)
+    cover, stego, msg, out = wl.allocate(dev)
+    status = torch.zeros(wl.count, dtype=torch.int32, device=dev)
+    lens = torch.zeros(wl.count, dtype=torch.int32, device=dev)
+    ls = torch.zeros((wl.count, 2), dtype=torch.int32, device=dev)
+    pe, px = batch.Plan(wl.count), batch.Plan(wl.count)
+    pe.set_jobs(wl.jobs(api.OP_EMBED))
+    px.set_jobs(wl.jobs(api.OP_EXTRACT))
+    emb_bytes = float(sum(embed_bytes(int(n), int(ln)) for n, ln in zip(wl.n, wl.len)))
+    ext_bytes = float(sum(extract_bytes(int(n), int(ln), int(k)) for n, ln, k in zip(wl.n, wl.len, wl.k)))
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    L = lib()
+    cb, sb, mb, ob, lb = cover.data_ptr(), stego.data_ptr(), msg.data_ptr(), out.data_ptr(), ls.data_ptr()
+    args_e = [(cb + int(c), sb + int(c), int(n), mb + int(m), int(ln), int(k))
+              for c, n, m, ln, k in zip(wl.cover_off, wl.n, wl.msg_off, wl.len, wl.k)]
+    args_x = [(sb + int(c), int(n), int(k), ob + int(m), int(ln), lb + 8 * i, lb + 8 * i + 4)
+              for i, (c, n, m, ln, k) in enumerate(zip(wl.cover_off, wl.n, wl.msg_off, wl.len, wl.k))]
+
+    def loop_embed():
+        for a in args_e:
+            L.lsb_embed(a[0], a[1], a[2], a[3], a[4], a[5], sp)
+
+    def loop_extract():
+        for a in args_x:
+            L.lsb_extract(a[0], a[1], a[2], a[3], a[4], a[5], a[6], sp)
+
+    def timed(fn):
+        ts, gs = [], []
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            gs.append(e0.elapsed_time(e1) * 1e-3)
+        return min(ts[1:]), min(gs[1:])
+
+    res = {}
+    for name, fn, b in [("batched_embed", lambda: pe.run(cover, stego, msg, lens, status), emb_bytes),
+                        ("loop_embed", loop_embed, emb_bytes),
+                        ("batched_extract", lambda: px.run(None, stego, out, lens, status), ext_bytes),
+                        ("loop_extract", loop_extract, ext_bytes)]:
+        wall, gpu = timed(fn)
+        res[name] = {"wall_ms": round(wall * 1e3, 3), "gpu_ms": round(gpu * 1e3, 3),
+                     "GBps_wall": round(b / wall / 1e9, 1)}
+        log_fn("%s: %.2f ms wall (%.1f GB/s)" % (name, wall * 1e3, b / wall / 1e9))
+    assert bool((status == 0).all()) and bool((ls[:, 1] == 0).all())
+    assert torch.equal(out, msg), "batched/loop extract lost messages"
+    pe.close()
+    px.close()
+    res["speedup_embed"] = round(res["loop_embed"]["wall_ms"] / res["batched_embed"]["wall_ms"], 3)
+    res["speedup_extract"] = round(res["loop_extract"]["wall_ms"] / res["batched_extract"]["wall_ms"], 3)
+    res["jobs"] = wl.count
+    res["cover_bytes"] = int(wl.n.sum())
+    return res, (wl, cover, msg)
+
+
+def bench_serving(api, serve, dev, pool, log_fn, rates=(2000.0, 10000.0, 50000.0), seconds=1.0,
+                  budget=64 << 30):
+    """Open-loop Poisson request streams over the device-resident 4096-cover
+    pool, 50/50 embed/extract, admission by a 64 GB HBM budget."""
+    import torch
+
+    wl, cover, msg = pool
+    arena = torch.empty(budget, dtype=torch.uint8, device=dev)
+    out = {}
+    for rate in rates:
+        count = int(rate * seconds)
+        req, _ = serve.poisson_requests(wl, rate, count, seed=501)
+        res, st = serve.serve(arena, cover, msg, req, max_batch=256, n_slots=4, keep_outputs=False)
+        ok = int((res["status"] == 0).sum())
+        out["%dk" % int(rate / 1000)] = {
+            "requests": count, "ok": ok, "GBps": round(st["gbps"], 1), "p50_ms": round(st["p50_ms"], 3),
+            "p99_ms": round(st["p99_ms"], 3), "max_ms": round(st["max_ms"], 3),
+            "mean_batch": round(st["mean_batch"], 2), "launches": st["launches"], "evictions": st["evictions"],
+            "stalls": st["admission_stalls"], "peak_budget_GB": round(st["peak_arena_bytes"] / 1e9, 2)}
+        log_fn("serving %d req/s: %s" % (rate, out["%dk" % int(rate / 1000)]))
+    del arena
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +170,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 4096-cover batched comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving streams")
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would take "
@@ -147,6 +245,18 @@ def main():
             assert st[ki, j, 1] == 0 and st[ki, j, 0] == msgs_np[k].size, (k, j, st[ki, j])
         assert torch.equal(outs[k][(args.warmup + args.steps) % SETS], msgs[k]), "extract mismatch k=%d" % k
 
+    # context: a plain device-to-device copy of the same cover size
+    cp_ms = []
+    for _ in range(4):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        stegos[1][0].copy_(covers[2])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        cp_ms.append(e0.elapsed_time(e1))
+    copy_ref = {"bytes": 2 * n, "us_min": round(min(cp_ms[1:]) * 1e3, 2),
+                "GBps": round(2 * n / (min(cp_ms[1:]) * 1e-3) / 1e9, 1)}
+
     per = {}
     for (op, k) in ev[0]:
         ms = [e[(op, k)][0].elapsed_time(e[(op, k)][1]) for e in ev]
@@ -174,7 +284,19 @@ def main():
                    "cover_bytes": n, "ks": list(KS), "buffer_sets": SETS},
         "roofline": roofline,
         "per_launch": per,
+        "copy_reference": copy_ref,
     }
+    if not args.no_batched:
+        from paper_0912_0947_amd import batch, serve
+
+        del covers, stegos, outs
+        torch.cuda.empty_cache()
+        log("batched (4096 uneven covers) ...")
+        result["batched"], pool = bench_batched(api, batch, dev, log)
+        if not args.no_serving:
+            result["serving"] = bench_serving(api, serve, dev, pool, log, seconds=args.serve_seconds)
+        del pool
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one step ...")
         result["cpu_baseline"] = cpu_baseline(cover_np, msgs_np)

@@ -190,6 +190,71 @@ int lsb_autotune(int op, int k, uint64_t n, uint8_t *cover, uint8_t *stego,
 int lsb_batch_tune_get(lsb_launch_cfg *cfg, int64_t *tile_vectors);
 int lsb_batch_tune_set(const lsb_launch_cfg *cfg, int64_t tile_vectors);
 
+/* ------------------------------------------------------------------------
+ * Serving loop: an open-loop stream of embed and extract requests served
+ * with continuous batching.  Requests are admitted in arrival order when the
+ * HBM budget (the caller's arena) has room for their outputs; admitted
+ * requests are packed into the next batched launch on any free slot (one
+ * plan + stream each), so batches overlap on the device and requests that
+ * arrive while others run join the next launch.  Stego buffers stay device
+ * resident until an extract consumes them (then they are freed) or the budget
+ * needs their space (oldest first, counted as evictions).
+ */
+typedef struct lsb_server_cfg {
+    uint8_t *arena;             /* device memory for stego and message outputs */
+    uint64_t arena_bytes;       /* its size: the HBM admission budget          */
+    const uint8_t *cover_pool;  /* device-resident covers (requests index it)  */
+    const uint8_t *msg_pool;    /* device-resident messages                    */
+    int32_t max_batch;          /* jobs per launch, 1..65536                   */
+    int32_t n_slots;            /* launches in flight, 1..16                   */
+    int32_t keep_outputs;       /* 1: never free or evict outputs (checking)   */
+    int32_t reserved;           /* must be 0                                   */
+} lsb_server_cfg;
+
+typedef struct lsb_request {
+    double arrival_s;   /* scheduled arrival, seconds after the run starts     */
+    uint64_t cover_off; /* embed: cover bytes [cover_off, +n) of cover_pool    */
+    uint64_t n;
+    uint64_t msg_off;   /* embed: message bytes [msg_off, +len) of msg_pool    */
+    uint32_t len;
+    uint8_t k;          /* embed: bits per byte                                */
+    uint8_t op;         /* LSB_OP_EMBED, or LSB_OP_EXTRACT of a live stego     */
+    uint16_t reserved;  /* must be 0                                           */
+    int64_t target;     /* extract: index of the embed request whose stego to
+                           read, or -1 for the oldest live one; an extract with
+                           no live stego to read is served as an embed         */
+} lsb_request;
+
+typedef struct lsb_result {
+    double admit_s, launch_s, done_s; /* seconds after the run starts          */
+    uint64_t out_off;  /* arena offset of the output (stego for embed, message
+                          for extract); UINT64_MAX once freed or evicted       */
+    int32_t status;    /* device status of the job, or LSB_E_NOMEM if the
+                          request can never fit the budget                     */
+    uint32_t len;      /* message length (decoded, for extract)                */
+    int64_t target;    /* extract: the embed request it read; else -1         */
+    uint8_t op_run;    /* the operation actually served                        */
+    uint8_t k;
+    uint8_t reserved[6];
+} lsb_result;
+
+typedef struct lsb_serve_stats {
+    double makespan_s;        /* first arrival to last completion             */
+    double bytes;             /* algorithmic bytes of all served requests     */
+    double gbps;              /* bytes / makespan                             */
+    double p50_ms, p99_ms, max_ms, mean_ms; /* latency = done - arrival       */
+    int64_t launches, evictions, admission_stalls, rejected;
+    double mean_batch;
+    uint64_t peak_arena_bytes; /* high-water mark of the budget in use        */
+} lsb_serve_stats;
+
+/* Serve `n_requests` requests (sorted by arrival) in real time on the
+ * current device; returns when every request has completed.  results[i]
+ * describes request i.  Allocates its plans, streams and events on entry and
+ * frees them on exit; never allocates device memory outside cfg->arena. */
+int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *requests, int n_requests, lsb_result *results,
+              lsb_serve_stats *stats);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char *lsb_last_error(void);
 

@@ -46,6 +46,29 @@ class Job(ctypes.Structure):
 
 assert ctypes.sizeof(Job) == 48
 
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_uint64),
+                ("cover_pool", ctypes.c_void_p), ("msg_pool", ctypes.c_void_p),
+                ("max_batch", ctypes.c_int32), ("n_slots", ctypes.c_int32),
+                ("keep_outputs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("makespan_s", ctypes.c_double), ("bytes", ctypes.c_double), ("gbps", ctypes.c_double),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("launches", ctypes.c_int64), ("evictions", ctypes.c_int64),
+                ("admission_stalls", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("mean_batch", ctypes.c_double), ("peak_arena_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+assert ctypes.sizeof(ServerCfg) == 48 and ctypes.sizeof(ServeStats) == 104
+REQUEST_BYTES = 48
+RESULT_BYTES = 56
+
 _P = ctypes.c_void_p
 _U64 = ctypes.c_uint64
 _I64 = ctypes.c_int64
@@ -70,6 +93,7 @@ SIGNATURES = {
                           ctypes.POINTER(ctypes.c_double), _P]),
     "lsb_batch_tune_get": (_I, [ctypes.POINTER(LaunchCfg), ctypes.POINTER(_I64)]),
     "lsb_batch_tune_set": (_I, [ctypes.POINTER(LaunchCfg), _I64]),
+    "lsb_serve": (_I, [ctypes.POINTER(ServerCfg), _P, _I, _P, ctypes.POINTER(ServeStats)]),
     "lsb_last_error": (ctypes.c_char_p, []),
     "lsb_version": (ctypes.c_char_p, []),
 }

@@ -70,6 +70,13 @@ class BatchWorkload:
         out = torch.zeros(self.msg_bytes, dtype=torch.uint8, device=device)
         inputs.fill_uniform(cover, pixel_seed)
         inputs.fill_uniform(msg, msg_seed)
+        # zero the alignment gaps between messages so that whole-arena
+        # comparisons of messages and extract outputs are meaningful
+        ends = self.msg_off + self.len
+        starts = np.append(self.msg_off[1:], self.msg_bytes)
+        for a, b in zip(ends, starts):
+            if b > a:
+                msg[int(a):int(b)].zero_()
         return cover, stego, msg, out
 
 

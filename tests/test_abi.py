@@ -55,19 +55,30 @@ def test_capacity_is_host_only(lib):
 
 def test_tune_table_roundtrip(lib):
     from paper_0912_0947_amd._lib import LaunchCfg
-    cfg = LaunchCfg()
-    assert lib.lsb_tune_get(0, 1, 1 << 27, ctypes.byref(cfg)) == 0
-    old = LaunchCfg(cfg.block, cfg.unroll, cfg.blocks_per_cu, cfg.nontemporal)
+    old27, old26 = LaunchCfg(), LaunchCfg()
+    assert lib.lsb_tune_get(0, 1, 1 << 27, ctypes.byref(old27)) == 0
+    assert lib.lsb_tune_get(0, 1, 1 << 26, ctypes.byref(old26)) == 0
     new = LaunchCfg(512, 4, 2, 1)
     assert lib.lsb_tune_set(0, 1, 27, ctypes.byref(new)) == 0
     got = LaunchCfg()
     lib.lsb_tune_get(0, 1, (1 << 27) + 5, ctypes.byref(got))
     assert got.as_dict() == new.as_dict()
     lib.lsb_tune_get(0, 1, 1 << 26, ctypes.byref(got))
-    assert got.as_dict() == old.as_dict()  # other buckets untouched
-    assert lib.lsb_tune_set(0, 1, 27, ctypes.byref(old)) == 0
+    assert got.as_dict() == old26.as_dict()  # other buckets untouched
+    assert lib.lsb_tune_set(0, 1, 27, ctypes.byref(old27)) == 0
     bad = LaunchCfg(100, 3, 0, 0)
     assert lib.lsb_tune_set(0, 1, 27, ctypes.byref(bad)) == -1
+
+
+def test_stored_tuning_table_is_valid():
+    """The committed table loads, covers every (op, k) and holds valid
+    configurations only."""
+    import json
+
+    from paper_0912_0947_amd import tune
+    table = json.load(open(tune.TABLE))
+    assert {(e["op"], e["k"]) for e in table["entries"]} == {(op, k) for op in (0, 1) for k in range(1, 9)}
+    assert tune.load() is True
 
 
 def test_no_cpu_fallback(monkeypatch, tmp_path):

@@ -1,0 +1,116 @@
+"""GPU tests of the serving loop: every request's result is the same alone
+and in the mix (tolerance 0), the HBM budget holds, and requests that can
+never fit fail alone."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_0912_0947_amd import api, serve
+from paper_0912_0947_amd._lib import E_NOMEM, OK, OP_EMBED, OP_EXTRACT
+from paper_0912_0947_amd.workloads import BatchWorkload
+
+from gpu_helpers import DEV, assert_bytes_equal, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pool():
+    wl = BatchWorkload(96, oracle.capacity, seed=611, lo=16, hi=600, ks=(1, 2, 3, 4, 8))
+    cover, _, msg, _ = wl.allocate(DEV, pixel_seed=612, msg_seed=613)
+    return wl, cover, msg
+
+
+def _check_results(wl, cover, msg, arena, req, res, ids):
+    """Replay every served request alone through the single-call API and
+    compare byte for byte; check a sample against the oracle."""
+    scratch = torch.empty(int(wl.n.max()) + 256, dtype=torch.uint8, device=DEV)
+    n_extract = 0
+    for i, r in enumerate(res):
+        assert r["status"] == OK, "request %d status %d" % (i, r["status"])
+        if r["op_run"] == OP_EMBED:
+            c0, n, m0, ln, k = int(req[i]["cover_off"]), int(req[i]["n"]), int(req[i]["msg_off"]), int(req[i]["len"]), int(req[i]["k"])
+            alone = api.embed(cover[c0:c0 + n], msg[m0:m0 + ln], k, out=scratch[:n])
+            o = int(r["out_off"])
+            assert torch.equal(arena[o:o + n], alone), "embed request %d differs from its single call" % i
+        else:
+            n_extract += 1
+            t = int(r["target"])
+            assert 0 <= t < i and res[t]["op_run"] == OP_EMBED
+            ln = int(res[t]["len"])
+            assert int(r["len"]) == ln
+            o, m0 = int(r["out_off"]), int(req[t]["msg_off"])
+            st = int(res[t]["out_off"])
+            alone = api.extract_sync(arena[st:st + int(req[t]["n"])], int(res[t]["k"]))
+            assert torch.equal(arena[o:o + ln], alone), "extract request %d differs from its single call" % i
+            assert torch.equal(arena[o:o + ln], msg[m0:m0 + ln]), "extract request %d lost the message" % i
+    # oracle on a few embeds
+    emb = [i for i in range(len(res)) if res[i]["op_run"] == OP_EMBED][:5]
+    for i in emb:
+        c0, n, m0, ln, k = int(req[i]["cover_off"]), int(req[i]["n"]), int(req[i]["msg_off"]), int(req[i]["len"]), int(req[i]["k"])
+        rc, want = oracle.embed(to_host(cover[c0:c0 + n]), to_host(msg[m0:m0 + ln]), k)
+        o = int(res[i]["out_off"])
+        assert_bytes_equal(to_host(arena[o:o + n]), want, "served embed %d vs oracle" % i)
+    return n_extract
+
+
+@pytest.mark.parametrize("rate,slots,max_batch", [(20000.0, 4, 64), (200000.0, 2, 16), (2000.0, 1, 256)])
+def test_mix_equals_alone(pool, rate, slots, max_batch):
+    wl, cover, msg = pool
+    req, ids = serve.poisson_requests(wl, rate, 600, seed=621)
+    arena = torch.empty(int(wl.n.sum()) * 4 + (64 << 20), dtype=torch.uint8, device=DEV)
+    res, stats = serve.serve(arena, cover, msg, req, max_batch=max_batch, n_slots=slots, keep_outputs=True)
+    assert stats["rejected"] == 0 and stats["evictions"] == 0
+    n_extract = _check_results(wl, cover, msg, arena, req, res, ids)
+    assert n_extract > 50  # the mix really contains extracts
+    assert stats["launches"] >= 1 and stats["p99_ms"] >= stats["p50_ms"] > 0
+    assert np.all(res["done_s"] >= res["launch_s"]) and np.all(res["launch_s"] >= res["admit_s"])
+    assert np.all(res["admit_s"] + 1e-9 >= req["arrival_s"])
+
+
+def test_budget_bounds_memory_and_evicts(pool):
+    """A budget of a few covers: admission waits for memory, resident stego
+    buffers are evicted oldest first, the high-water mark never exceeds the
+    budget, and every served request still succeeds."""
+    wl, cover, msg = pool
+    req, ids = serve.poisson_requests(wl, 50000.0, 800, seed=631, extract_frac=0.3)
+    budget = int(np.sort(wl.n)[-4:].sum()) * 2 + (1 << 16)
+    arena = torch.empty(budget, dtype=torch.uint8, device=DEV)
+    res, stats = serve.serve(arena, cover, msg, req, max_batch=32, n_slots=4, keep_outputs=False)
+    assert stats["peak_arena_bytes"] <= budget
+    assert stats["rejected"] == 0
+    assert stats["evictions"] > 0
+    assert np.all(res["status"] == OK)
+    ext = res["op_run"] == OP_EXTRACT
+    assert ext.any()
+    for i in np.nonzero(ext)[0]:
+        assert res[i]["len"] == res[int(res[i]["target"])]["len"]  # decoded header = embedded length
+
+
+def test_request_that_never_fits_fails_alone(pool):
+    wl, cover, msg = pool
+    req, ids = serve.poisson_requests(wl, 10000.0, 50, seed=641, extract_frac=0.0)
+    order = np.argsort(wl.n)
+    small = order[: len(order) // 2]
+    pick = small[inputs_rng_ints(642, len(req), len(small))]
+    for f in ("cover_off", "n", "msg_off", "len", "k"):
+        src = {"cover_off": wl.cover_off, "n": wl.n, "msg_off": wl.msg_off, "len": wl.len, "k": wl.k}[f]
+        req[f] = src[pick]
+    big = 17
+    j = order[-1]
+    req[big]["cover_off"], req[big]["n"], req[big]["msg_off"] = wl.cover_off[j], wl.n[j], wl.msg_off[j]
+    req[big]["len"], req[big]["k"] = wl.len[j], wl.k[j]
+    budget = int(wl.n[small].max()) * 3 + 8192
+    assert budget < int(wl.n[j])
+    arena = torch.empty(budget, dtype=torch.uint8, device=DEV)
+    res, stats = serve.serve(arena, cover, msg, req, max_batch=8, n_slots=2, keep_outputs=False)
+    assert res[big]["status"] == E_NOMEM
+    others = np.arange(len(req)) != big
+    assert np.all(res["status"][others] == OK)
+    assert stats["rejected"] == 1
+
+
+def inputs_rng_ints(seed, count, high):
+    from paper_0912_0947_amd import inputs
+    return inputs.rng(seed).integers(0, high, size=count)
