@@ -47,6 +47,26 @@ def extract_bytes(n, ln, k):
     return -(-8 * s // k) + ln
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "plain_8192x8192x3_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0912_0947_amd", "csrc", f) for f in ("lsb_device.hpp", "lsb_plain.hip")]
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter profile, or
+    None when the kernel sources or the selected kernel changed since."""
+    import hashlib
+    import re
+
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    text = open(TRAFFIC_PROFILE).read()
+    got = dict(re.findall(r"^(kernel|source_sha256|traffic_bytes_per_launch): (.+)$", text, flags=re.M))
+    sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
+    if got.get("source_sha256") != sha or got.get("kernel") != kernel:
+        return None
+    return int(got["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(cover_np, msgs):
     """The oracle as it stands, single-threaded, on one full step of the
     workload (embed + extract at k = 1, 2, 4 on the whole cover)."""
@@ -210,19 +230,20 @@ def main():
     stream = torch.cuda.current_stream()
     step_bytes = sum(embed_bytes(n, msgs_np[k].size) + extract_bytes(n, msgs_np[k].size, k) for k in KS)
 
+    L = lib()
+
     def step(it, events=None):
+        # events[(op, k)] = (start, stop): bound to the launch itself through
+        # lsb_time_next_launch, so they mark the kernel's own begin and end
         j = it % SETS
         jx = (it + 1) % SETS  # extract reads a stego written an earlier step
         for ki, k in enumerate(KS):
             if events is not None:
-                events[("embed", k)][0].record(stream)
+                L.lsb_time_next_launch(*events[("embed", k)])
             api.embed(covers[j], msgs[k], k, out=stegos[k][j])
             if events is not None:
-                events[("embed", k)][1].record(stream)
-                events[("extract", k)][0].record(stream)
+                L.lsb_time_next_launch(*events[("extract", k)])
             api.extract(stegos[k][jx], k, out=outs[k][jx], len_status=ls[ki, jx])
-            if events is not None:
-                events[("extract", k)][1].record(stream)
 
     for it in range(args.warmup):
         step(it)
@@ -231,6 +252,10 @@ def main():
     # timed region: K steps, per-launch HIP events on the launch stream
     ev = [{(op, k): (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for op in ("embed", "extract") for k in KS} for _ in range(args.steps)]
+    for e in ev:  # create the HIP events before the timed region
+        for a, b in e.values():
+            a.record(stream)
+            b.record(stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for it in range(args.steps):
@@ -269,11 +294,13 @@ def main():
     value = step_bytes * args.steps / wall / 1e9
     dom = per["embed_k1"]
     achieved = dom["bytes"] / (dom["us_mean"] * 1e-6) / 1e9
-    traffic = None
+    cfg = api.tune_get(api.OP_EMBED, 1, n)
+    kernel = "lsb_embed_kernel<1, %d, %s>" % (cfg["unroll"], "true" if cfg["nontemporal"] else "false")
+    traffic = stored_traffic(kernel)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "lsb_embed_kernel<1,*,*> (k=1 embed, 8192x8192x3, full capacity)",
-                "algorithmic_bytes_per_launch": dom["bytes"]}
+                "kernel": kernel + " (k=1 embed, 8192x8192x3 cover, full-capacity message)",
+                "algorithmic_bytes_per_launch": dom["bytes"], "launch_us_mean": dom["us_mean"]}
 
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,

@@ -255,6 +255,13 @@ typedef struct lsb_serve_stats {
 int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *requests, int n_requests, lsb_result *results,
               lsb_serve_stats *stats);
 
+/* Measurement support: the next plain embed or extract kernel launched by
+ * the calling thread records `start_event` and `stop_event` (hipEvent_t
+ * handles passed as void*, created with timing enabled) at the kernel's own
+ * begin and end, so that per-launch durations exclude queueing and marker
+ * packets.  Applies to one launch, then clears.  Both may be NULL to clear. */
+int lsb_time_next_launch(void *start_event, void *stop_event);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char *lsb_last_error(void);
 

@@ -14,6 +14,8 @@
 // lane moves 16 contiguous cover bytes per access, a wave 1 KiB, the grid
 // covers the whole image in one launch, and every output byte has exactly
 // one writer.
+#include <hip/hip_ext.h>
+
 #include "lsb_host.hpp"
 
 namespace lsb {
@@ -168,12 +170,16 @@ int launch_embed(const Span &s0, const lsb_launch_cfg &c, hipStream_t stream) {
         if (!count) return LSB_OK;
         uint64_t blocks = ceil_div(count, 256);
         if (blocks > 65536) blocks = 65536;
-        hipLaunchKernelGGL(lsb_embed_bytes_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, s, count);
+        hipEvent_t e0, e1;
+        take_launch_events(&e0, &e1);
+        hipExtLaunchKernelGGL(lsb_embed_bytes_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, e0, e1, 0, s, count);
     } else {
         const Ranges r = embed_ranges(s);
         if (!r.count) return LSB_OK;
         EmbedFn fn = embed_fn(s.k, c.unroll, c.nontemporal);
-        hipLaunchKernelGGL(fn, dim3(grid_for(c, r.count)), dim3(c.block), 0, stream, s);
+        hipEvent_t e0, e1;
+        take_launch_events(&e0, &e1);
+        hipExtLaunchKernelGGL(fn, dim3(grid_for(c, r.count)), dim3(c.block), 0, stream, e0, e1, 0, s);
     }
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? LSB_OK : hip_fail(e, "embed kernel launch");
@@ -187,12 +193,16 @@ int launch_extract(const Span &s0, int header, uint64_t out_cap, uint32_t *len_o
         uint64_t bytes = max_vectors * 2 * (uint64_t)s.k;  // output stream bytes bound
         uint64_t blocks = ceil_div(bytes ? bytes : 1, 256);
         if (blocks > 65536) blocks = 65536;
-        hipLaunchKernelGGL(lsb_extract_bytes_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, s, header,
-                           out_cap, len_out, status_out);
+        hipEvent_t e0, e1;
+        take_launch_events(&e0, &e1);
+        hipExtLaunchKernelGGL(lsb_extract_bytes_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, e0, e1, 0, s,
+                              header, out_cap, len_out, status_out);
     } else {
         ExtractFn fn = extract_fn(s.k, c.unroll, c.nontemporal);
-        hipLaunchKernelGGL(fn, dim3(grid_for(c, max_vectors)), dim3(c.block), 0, stream, s, header, out_cap,
-                           len_out, status_out);
+        hipEvent_t e0, e1;
+        take_launch_events(&e0, &e1);
+        hipExtLaunchKernelGGL(fn, dim3(grid_for(c, max_vectors)), dim3(c.block), 0, stream, e0, e1, 0, s, header,
+                              out_cap, len_out, status_out);
     }
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? LSB_OK : hip_fail(e, "extract kernel launch");

@@ -24,6 +24,20 @@ int fail(int code, const char *fmt, ...) {
 
 void clear_error() { g_error.clear(); }
 
+static thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+
+void take_launch_events(hipEvent_t *start, hipEvent_t *stop) {
+    *start = g_ev_start;
+    *stop = g_ev_stop;
+    g_ev_start = g_ev_stop = nullptr;
+}
+
+int set_launch_events(void *start, void *stop) {
+    g_ev_start = (hipEvent_t)start;
+    g_ev_stop = (hipEvent_t)stop;
+    return 0;
+}
+
 int hip_fail(hipError_t e, const char *what) {
     return fail(LSB_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
@@ -85,6 +99,8 @@ extern "C" {
 const char *lsb_last_error(void) { return g_error.c_str(); }
 
 const char *lsb_version(void) { return "liblsb 0.1 gfx950"; }
+
+int lsb_time_next_launch(void *start_event, void *stop_event) { return set_launch_events(start_event, stop_event); }
 
 int lsb_tune_get(int op, int k, uint64_t n, lsb_launch_cfg *cfg) {
     if ((op != LSB_OP_EMBED && op != LSB_OP_EXTRACT) || k < 1 || k > 8 || !cfg)

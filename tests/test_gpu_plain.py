@@ -239,3 +239,40 @@ def test_config2_full_size(k, cfg2_cover):
     ls = ls.cpu().numpy()
     assert ls[1] == OK and ls[0] == cap
     assert_bytes_equal(to_host(out), msg_np, "cfg2 message k=%d" % k)
+
+
+def test_config3_video_full_clip():
+    """600 frames of 1080x1920x3 (3.73 GB, device resident), k = 1, one
+    message at 50 % capacity (|S| = 233,280,000 bytes, ending exactly at the
+    end of frame 299).  Whole-clip embed/extract equal 600 per-frame raw
+    calls byte for byte; sampled frames match the oracle."""
+    frames, h, w = 600, 1080, 1920
+    fb = h * w * 3
+    clip = inputs.video_frames(frames, h, w, device=DEV).view(-1)
+    n = clip.numel()
+    ln = (n * 1) // 8 // 2 - 4  # |S| = half the clip's capacity in bytes
+    assert 4 + ln == 233_280_000
+    msg = torch.empty(ln, dtype=torch.uint8, device=DEV)
+    inputs.fill_uniform(msg, 303)
+    whole = api.embed(clip, msg, 1)
+    # the same stream as raw bytes: 4 header bytes (big endian) then the message
+    stream = torch.empty(4 + ln, dtype=torch.uint8, device=DEV)
+    stream[:4] = torch.tensor(list(ln.to_bytes(4, "big")), dtype=torch.uint8)
+    stream[4:] = msg
+    per = torch.empty_like(clip)
+    for f in range(frames):
+        api.embed_raw(clip[f * fb:(f + 1) * fb], f * fb, stream, 8 * (4 + ln), 1, out=per[f * fb:(f + 1) * fb])
+    assert torch.equal(per, whole), "per-frame raw embed differs from the whole-clip embed"
+    assert torch.equal(whole[300 * fb:], clip[300 * fb:]), "frames past the stream changed"
+    out = api.extract_sync(whole, 1)
+    assert out.numel() == ln and torch.equal(out, msg)
+    back = torch.zeros_like(stream)
+    for f in range(frames):
+        api.extract_raw(whole[f * fb:(f + 1) * fb], f * fb, back, 8 * (4 + ln), 1)
+    assert torch.equal(back, stream)
+    stream_np = to_host(stream)
+    for f in (0, 1, 150, 299, 300, 599):
+        sl = slice(f * fb, (f + 1) * fb)
+        rc, want = oracle.embed_raw(to_host(clip[sl]), f * fb, stream_np, 8 * (4 + ln), 1)
+        assert rc == 0
+        assert_bytes_equal(to_host(whole[sl]), want, "frame %d vs oracle" % f)
