@@ -193,6 +193,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-cover batched comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving streams")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--events", choices=("dominant", "all"), default="dominant",
+                    help="launches timed with kernel-bound events inside the timed region: the dominant "
+                         "k=1 embed only (others timed in a short pass afterwards), or all six")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would take "
@@ -238,10 +241,10 @@ def main():
         j = it % SETS
         jx = (it + 1) % SETS  # extract reads a stego written an earlier step
         for ki, k in enumerate(KS):
-            if events is not None:
+            if events is not None and ("embed", k) in events:
                 L.lsb_time_next_launch(*events[("embed", k)])
             api.embed(covers[j], msgs[k], k, out=stegos[k][j])
-            if events is not None:
+            if events is not None and ("extract", k) in events:
                 L.lsb_time_next_launch(*events[("extract", k)])
             api.extract(stegos[k][jx], k, out=outs[k][jx], len_status=ls[ki, jx])
 
@@ -250,25 +253,41 @@ def main():
     torch.cuda.synchronize()
 
     # timed region: K steps, per-launch HIP events on the launch stream
-    ev = [{(op, k): (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for op in ("embed", "extract") for k in KS} for _ in range(args.steps)]
-    for e in ev:  # create the HIP events before the timed region
-        for a, b in e.values():
-            a.record(stream)
-            b.record(stream)
-    torch.cuda.synchronize()
+    all_keys = [(op, k) for op in ("embed", "extract") for k in KS]
+    timed_keys = all_keys if args.events == "all" else [("embed", 1)]
+
+    def make_events(steps, keys):
+        ev = [{key: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for key in keys}
+              for _ in range(steps)]
+        for e in ev:  # create the HIP events outside any timed region
+            for a, b in e.values():
+                a.record(stream)
+                b.record(stream)
+        torch.cuda.synchronize()
+        return ev
+
+    ev = make_events(args.steps, timed_keys)
     t0 = time.perf_counter()
     for it in range(args.steps):
         step(args.warmup + it, ev[it])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # per-launch table for the launches that the timed region did not time
+    last_it = args.warmup + args.steps - 1
+    detail = ev
+    if args.events != "all":
+        detail = make_events(3, all_keys)
+        for it in range(3):
+            last_it += 1
+            step(last_it, detail[it])
+        torch.cuda.synchronize()
 
     # correctness of the last step's outputs (device-side compare, no copies)
     st = ls.cpu().numpy()
     for ki, k in enumerate(KS):
         for j in range(SETS):
             assert st[ki, j, 1] == 0 and st[ki, j, 0] == msgs_np[k].size, (k, j, st[ki, j])
-        assert torch.equal(outs[k][(args.warmup + args.steps) % SETS], msgs[k]), "extract mismatch k=%d" % k
+        assert torch.equal(outs[k][(last_it + 1) % SETS], msgs[k]), "extract mismatch k=%d" % k
 
     # context: a plain device-to-device copy of the same cover size
     cp_ms = []
@@ -283,8 +302,9 @@ def main():
                 "GBps": round(2 * n / (min(cp_ms[1:]) * 1e-3) / 1e9, 1)}
 
     per = {}
-    for (op, k) in ev[0]:
-        ms = [e[(op, k)][0].elapsed_time(e[(op, k)][1]) for e in ev]
+    for (op, k) in all_keys:
+        src = ev if (op, k) in timed_keys else detail
+        ms = [e[(op, k)][0].elapsed_time(e[(op, k)][1]) for e in src]
         ln = msgs_np[k].size
         b = embed_bytes(n, ln) if op == "embed" else extract_bytes(n, ln, k)
         med = statistics.median(ms)

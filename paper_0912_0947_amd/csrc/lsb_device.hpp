@@ -376,13 +376,36 @@ __device__ __forceinline__ void embed_walk(const Span &s, const Ranges &r, uint6
     }
 }
 
+// Store the stream bytes of one fast wave group whose stego vectors are in c.
+template <int K, int UNR>
+__device__ __forceinline__ void extract_store_group(const Span &s, uintptr_t out_base, uint64_t u0,
+                                                    const u32x4 *c, uint32_t lane) {
+#pragma unroll
+    for (int j = 0; j < UNR; ++j) {
+        const uint64_t u = u0 + (uint64_t)j * 64 + lane;
+        uint32_t w[Chunk<K>::NW];
+        extract_vec<K>(c[j], w);
+        uint8_t *p = reinterpret_cast<uint8_t *>(out_base + 2 * K * u);
+        if (s.words) {
+            store_chunk_words<K>(p, w);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 2 * K; ++i) p[i] = (uint8_t)(w[i >> 2] >> (24 - 8 * (i & 3)));
+        }
+    }
+}
+
+__host__ __device__ inline uintptr_t extract_out_base(const Span &s) {
+    return (uintptr_t)s.out + stream_byte0(s) - s.hdr_len;
+}
+
 template <int K, int UNR, bool NT>
 __device__ __forceinline__ void extract_walk(const Span &s, const Ranges &r, uint64_t v_begin,
                                              uint64_t v_end, uint64_t wave, uint64_t n_waves,
                                              uint32_t lane) {
     constexpr uint64_t G = 64 * UNR;
     const uint64_t sb = stream_byte0(s);
-    const uintptr_t out_base = (uintptr_t)s.out + sb - s.hdr_len;
+    const uintptr_t out_base = extract_out_base(s);
     for (uint64_t u0 = v_begin + wave * G; u0 < v_end; u0 += n_waves * G) {
         const uint64_t u_hi = u0 + G;
         if (u0 >= r.fast_begin && u_hi <= r.fast_end && u_hi <= v_end) {
@@ -390,19 +413,7 @@ __device__ __forceinline__ void extract_walk(const Span &s, const Ranges &r, uin
 #pragma unroll
             for (int j = 0; j < UNR; ++j)
                 c[j] = load16<NT>(s.src + 16 * (u0 + (uint64_t)j * 64 + lane));
-#pragma unroll
-            for (int j = 0; j < UNR; ++j) {
-                const uint64_t u = u0 + (uint64_t)j * 64 + lane;
-                uint32_t w[Chunk<K>::NW];
-                extract_vec<K>(c[j], w);
-                uint8_t *p = reinterpret_cast<uint8_t *>(out_base + 2 * K * u);
-                if (s.words) {
-                    store_chunk_words<K>(p, w);
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 2 * K; ++i) p[i] = (uint8_t)(w[i >> 2] >> (24 - 8 * (i & 3)));
-                }
-            }
+            extract_store_group<K, UNR>(s, out_base, u0, c, lane);
         } else {
             for (int j = 0; j < UNR; ++j) {
                 const uint64_t u = u0 + (uint64_t)j * 64 + lane;

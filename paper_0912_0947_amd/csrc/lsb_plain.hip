@@ -39,27 +39,51 @@ __global__ void __launch_bounds__(1024) lsb_embed_kernel(Span s) {
 template <int K, int UNR, bool NT>
 __global__ void __launch_bounds__(1024)
     lsb_extract_kernel(Span s, int header, uint64_t out_cap, uint32_t *len_out, int32_t *status_out) {
+    constexpr uint64_t G = 64 * UNR;
     const uint32_t lane = threadIdx.x & 63u;
-    if (header) {
-        uint32_t len = 0;
-        int status = LSB_E_HEADER;
-        if ((uint64_t)K * s.n >= 32) {
-            len = decode_header(s.src, K, lane);
-            if (4 + (uint64_t)len > room_bytes(s.n, K)) status = LSB_E_HEADER;
-            else if ((uint64_t)len > out_cap) status = LSB_E_BUFFER;
-            else status = LSB_OK;
-        }
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            *len_out = len;
-            *status_out = status;
-        }
-        if (status != LSB_OK) return;
-        s.bits = 8 * (4 + (uint64_t)len);
-    }
-    const Ranges r = extract_ranges(s);
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    extract_walk<K, UNR, NT>(s, r, 0, r.count, wave, n_waves, lane);
+    if (!header) {
+        const Ranges r = extract_ranges(s);
+        extract_walk<K, UNR, NT>(s, r, 0, r.count, wave, n_waves, lane);
+        return;
+    }
+    // Header mode.  Lane j < 32 reads the stego byte holding stream bit j;
+    // while that load is in flight the wave already loads its first group
+    // of stego vectors whenever the group lies inside the buffer (the loads
+    // do not depend on the decoded length).
+    const bool fits = (uint64_t)K * s.n >= 32;
+    uint32_t hbyte = 0;
+    if (fits && lane < 32) hbyte = s.src[lane / K];
+    const uint64_t u_first = wave * G;
+    const bool pre = (u_first + G) * 16 <= s.n;
+    u32x4 c[UNR];
+    if (pre) {
+#pragma unroll
+        for (int j = 0; j < UNR; ++j) c[j] = load16<NT>(s.src + 16 * (u_first + (uint64_t)j * 64 + lane));
+    }
+    uint32_t len = 0;
+    int status = LSB_E_HEADER;
+    if (fits) {
+        const uint32_t bit = lane < 32 ? (hbyte >> (K - 1 - lane % K)) & 1u : 0u;
+        len = __builtin_bitreverse32((uint32_t)__ballot(bit));
+        if (4 + (uint64_t)len > room_bytes(s.n, K)) status = LSB_E_HEADER;
+        else if ((uint64_t)len > out_cap) status = LSB_E_BUFFER;
+        else status = LSB_OK;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *len_out = len;
+        *status_out = status;
+    }
+    if (status != LSB_OK) return;
+    s.bits = 8 * (4 + (uint64_t)len);
+    const Ranges r = extract_ranges(s);
+    uint64_t v_begin = 0;
+    if (pre && u_first >= r.fast_begin && u_first + G <= r.fast_end && u_first + G <= r.count) {
+        extract_store_group<K, UNR>(s, extract_out_base(s), u_first, c, lane);
+        v_begin = n_waves * G;  // the walk resumes at this wave's second group
+    }
+    extract_walk<K, UNR, NT>(s, r, v_begin, r.count, wave, n_waves, lane);
 }
 
 // Per-byte embed for buffers whose cover or stego pointer is not 16-byte
