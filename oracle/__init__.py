@@ -72,6 +72,14 @@ def _bind(path: str):
     lib.oracle_extract_raw.argtypes = [u8p, ctypes.c_uint64,
                                        ctypes.c_uint64, u8p,
                                        ctypes.c_uint64, ctypes.c_int]
+    lib.oracle_paper_capacity.restype = ctypes.c_uint64
+    lib.oracle_paper_capacity.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+    lib.oracle_paper_embed.restype = ctypes.c_int
+    lib.oracle_paper_embed.argtypes = [u8p, u8p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                       ctypes.c_uint32, u8p, ctypes.c_uint64]
+    lib.oracle_paper_extract.restype = ctypes.c_int
+    lib.oracle_paper_extract.argtypes = [u8p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                         ctypes.c_uint32, u8p, ctypes.c_uint64]
     return lib
 
 
@@ -157,3 +165,27 @@ def extract_raw(stego, t0: int, stream_bits: int, k: int, stream_out=None):
     rc = _load().oracle_extract_raw(_ptr(stego), stego.size, t0,
                                     _ptr(stream_out), stream_bits, k)
     return rc, stream_out
+
+
+# ---------------------------------------------------------------------------
+# The paper's own layout (2 bits per byte, one plane, greedy rows, strided
+# bit pairs).
+def paper_capacity(h: int, w: int) -> int:
+    return int(_load().oracle_paper_capacity(h, w))
+
+
+def paper_embed(cover, h: int, w: int, c: int, plane: int, data):
+    """Returns (status, stego) for an h x w x c cover (flat or shaped)."""
+    cover = _u8(cover)
+    data = _u8(data)
+    stego = cover.copy()
+    rc = _load().oracle_paper_embed(_ptr(cover), _ptr(stego), h, w, c, plane, _ptr(data), data.size)
+    return rc, stego
+
+
+def paper_extract(stego, h: int, w: int, c: int, plane: int, length: int):
+    """Returns (status, data bytes)."""
+    stego = _u8(stego)
+    out = np.zeros(max(length, 1), dtype=np.uint8)
+    rc = _load().oracle_paper_extract(_ptr(stego), h, w, c, plane, _ptr(out), length)
+    return rc, out[:length]

@@ -179,3 +179,89 @@ int oracle_extract(const uint8_t *stego, uint64_t n, int k,
     free(s);
     return rc;
 }
+
+/* ------------------------------------------------------------------------
+ * The paper's own layout.  Section VI: separate one plane (step 2), give
+ * each row a data chunk B with size(B)*4 <= size(A) (steps 4-5), and for
+ * block i = 0..3 and thread j = 0..L-1 take bits 2i+1..2i of B[j] (mask
+ * 0000 0011 << 2i, then shift right by 2i) into pixel A[L*i + j], whose low
+ * two bits are cleared with 1111 1100 (step 7).  Section VII: B starts at
+ * zero (step 4); for each i, j the low two bits of A[L*i + j], shifted left
+ * by 2i, are ORed into B[j] (step 6).
+ */
+uint64_t oracle_paper_capacity(uint32_t h, uint32_t w)
+{
+    return (uint64_t)h * (w / 4);
+}
+
+/* pixel x of row y of the plane */
+static uint64_t plane_index(uint32_t y, uint32_t x, uint32_t w, uint32_t c,
+                            uint32_t plane)
+{
+    return ((uint64_t)y * w + x) * c + plane;
+}
+
+int oracle_paper_embed(const uint8_t *cover, uint8_t *stego, uint32_t h,
+                       uint32_t w, uint32_t c, uint32_t plane,
+                       const uint8_t *data, uint64_t len)
+{
+    if (c == 0 || plane >= c)
+        return ORACLE_E_ARG;
+    if (len > oracle_paper_capacity(h, w))
+        return ORACLE_E_CAPACITY;
+    uint64_t n = (uint64_t)h * w * c;
+    if (n > 0 && (!cover || !stego))
+        return ORACLE_E_ARG;
+    if (len > 0 && !data)
+        return ORACLE_E_ARG;
+    if (stego != cover)
+        memcpy(stego, cover, (size_t)n);
+
+    uint64_t remaining = len, off = 0;
+    for (uint32_t y = 0; y < h && remaining > 0; ++y) {
+        uint64_t L = remaining < w / 4 ? remaining : w / 4; /* size(B) */
+        const uint8_t *B = data + off;
+        for (unsigned i = 0; i < 4; ++i) {
+            for (uint64_t j = 0; j < L; ++j) {
+                unsigned v = B[j];
+                v &= 3u << (2 * i);
+                v >>= 2 * i;
+                uint64_t at = plane_index(y, (uint32_t)(L * i + j), w, c, plane);
+                stego[at] = (uint8_t)((stego[at] & 0xFCu) | v);
+            }
+        }
+        off += L;
+        remaining -= L;
+    }
+    return ORACLE_OK;
+}
+
+int oracle_paper_extract(const uint8_t *stego, uint32_t h, uint32_t w,
+                         uint32_t c, uint32_t plane, uint8_t *data,
+                         uint64_t len)
+{
+    if (c == 0 || plane >= c)
+        return ORACLE_E_ARG;
+    if (len > oracle_paper_capacity(h, w))
+        return ORACLE_E_CAPACITY;
+    if (len > 0 && (!stego || !data))
+        return ORACLE_E_ARG;
+
+    uint64_t remaining = len, off = 0;
+    for (uint32_t y = 0; y < h && remaining > 0; ++y) {
+        uint64_t L = remaining < w / 4 ? remaining : w / 4;
+        uint8_t *B = data + off;
+        memset(B, 0, (size_t)L);
+        for (unsigned i = 0; i < 4; ++i) {
+            for (uint64_t j = 0; j < L; ++j) {
+                uint64_t at = plane_index(y, (uint32_t)(L * i + j), w, c, plane);
+                unsigned v = stego[at] & 3u;
+                v <<= 2 * i;
+                B[j] = (uint8_t)(B[j] | v);
+            }
+        }
+        off += L;
+        remaining -= L;
+    }
+    return ORACLE_OK;
+}

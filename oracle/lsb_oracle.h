@@ -74,6 +74,22 @@ int oracle_embed_raw(const uint8_t *cover, uint8_t *stego, uint64_t n,
 int oracle_extract_raw(const uint8_t *stego, uint64_t n, uint64_t t0,
                        uint8_t *stream_out, uint64_t stream_bits, int k);
 
+/* ---------------------------------------------------------------------
+ * The paper's own layout (Section VI steps 2-7, Section VII steps 2-6):
+ * 2 bits per byte, one colour plane `plane` of an h x w x c (HWC) image,
+ * the data split greedily over the rows in order (each row takes
+ * L = min(remaining, w/4) bytes, so that 4L <= w), and inside a row bit pair
+ * i (bits 2i+1..2i) of data byte j goes to pixel L*i + j of the plane.  No
+ * header: the caller passes the data length, as the paper's extract call
+ * does.  Capacity: h * floor(w/4) bytes (ORACLE_E_CAPACITY beyond it). */
+uint64_t oracle_paper_capacity(uint32_t h, uint32_t w);
+int oracle_paper_embed(const uint8_t *cover, uint8_t *stego, uint32_t h,
+                       uint32_t w, uint32_t c, uint32_t plane,
+                       const uint8_t *data, uint64_t len);
+int oracle_paper_extract(const uint8_t *stego, uint32_t h, uint32_t w,
+                         uint32_t c, uint32_t plane, uint8_t *data,
+                         uint64_t len);
+
 #ifdef __cplusplus
 }
 #endif

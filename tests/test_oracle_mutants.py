@@ -29,6 +29,13 @@ MUTANTS = {
     "capacity_off_by_one": ("uint64_t cap = room - 4;", "uint64_t cap = room - 3;"),
     "header_check_off_by_one": ("if (4 + (uint64_t)len > bits_to_bytes_floor(n, k))", "if (3 + (uint64_t)len > bits_to_bytes_floor(n, k))"),
     "tail_not_copied": ("stego[t] = cover[t]; /* past the stream: unchanged */", "stego[t] = 0;"),
+    "paper_pixel_index_swapped": ("uint64_t at = plane_index(y, (uint32_t)(L * i + j), w, c, plane);\n                stego[at]",
+                                  "uint64_t at = plane_index(y, (uint32_t)(4 * j + i), w, c, plane);\n                stego[at]"),
+    "paper_pair_not_shifted": ("                v >>= 2 * i;\n", "                v >>= 0;\n"),
+    "paper_rows_not_greedy": ("uint64_t L = remaining < w / 4 ? remaining : w / 4; /* size(B) */",
+                              "uint64_t L = w / 4 < remaining ? w / 4 : remaining; if (y % 2) L = remaining < 1 ? remaining : 1;"),
+    "paper_wrong_plane": ("return ((uint64_t)y * w + x) * c + plane;", "return ((uint64_t)y * w + x) * c;"),
+    "paper_extract_no_shift": ("                v <<= 2 * i;\n", "                v <<= 0;\n"),
     "buffer_check_missing": ("if ((uint64_t)len > out_cap)\n        return ORACLE_E_BUFFER;", "if (0)\n        return ORACLE_E_BUFFER;"),
 }
 
@@ -46,6 +53,7 @@ def test_mutant_is_caught(name, tmp_path):
                            "-o", str(lib), str(mutant_c)])
     env = dict(os.environ, LSB_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle.py")],
+                        os.path.join(ROOT, "tests", "test_oracle.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_paper.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "mutant %s survived every pin:\n%s" % (name, r.stdout[-2000:])
