@@ -159,6 +159,43 @@ def bench_batched(api, batch, dev, log_fn, reps=3):
     return res, (wl, cover, msg)
 
 
+def bench_paper_layout(api, lib_handle, cover, dev, reps=5):
+    """The paper's own layout (2 bits per byte in plane 0, greedy rows, bit
+    pair i of byte j in pixel L*i + j) on the 8192x8192x3 cover at full
+    capacity: one embed and one extract launch, kernel-bound event timing.
+    Algorithmic bytes: embed 2n + len; extract 4*len plane bytes + len."""
+    import torch
+
+    from paper_0912_0947_amd import inputs
+
+    h = w = 8192
+    cap = api.paper_capacity(h, w)
+    data = torch.empty(cap, dtype=torch.uint8, device=dev)
+    inputs.fill_uniform(data, 1401)
+    stego = torch.empty_like(cover)
+    out = torch.empty_like(data)
+    n = cover.numel()
+    res = {}
+    for name, fn, b in [("embed", lambda: api.paper_embed(cover, h, w, 3, 0, data, out=stego), 2 * n + cap),
+                        ("extract", lambda: api.paper_extract(stego, h, w, 3, 0, cap, out=out), 5 * cap)]:
+        ms = []
+        for r in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            e1.record()
+            torch.cuda.synchronize()
+            lib_handle.lsb_time_next_launch(e0, e1)
+            fn()
+            torch.cuda.synchronize()
+            if r:
+                ms.append(e0.elapsed_time(e1))
+        us = sorted(ms)[len(ms) // 2] * 1e3
+        res[name] = {"bytes": b, "us_median": round(us, 2), "GBps": round(b / (us * 1e-6) / 1e9, 1)}
+    assert torch.equal(out, data), "paper-layout round trip failed"
+    res["workload"] = "8192x8192x3 smooth cover, plane 0, %d data bytes (full capacity)" % cap
+    return res
+
+
 def bench_serving(api, serve, dev, pool, log_fn, rates=(2000.0, 10000.0, 50000.0), seconds=1.0,
                   budget=64 << 30):
     """Open-loop Poisson request streams over the device-resident 4096-cover
@@ -333,6 +370,8 @@ def main():
         "per_launch": per,
         "copy_reference": copy_ref,
     }
+    result["paper_layout"] = bench_paper_layout(api, L, covers[0], dev)
+
     if not args.no_batched:
         from paper_0912_0947_amd import batch, serve
 

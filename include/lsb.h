@@ -111,6 +111,30 @@ int lsb_extract_raw(const uint8_t *stego, uint64_t n, uint64_t t0,
                     void *stream);
 
 /* ------------------------------------------------------------------------
+ * The paper's own layout (Section VI steps 2-7, Section VII steps 2-6), kept
+ * for fidelity: 2 bits per byte in ONE colour plane `plane` of an h x w x c
+ * HWC image; the data is split greedily over the rows in order, row y taking
+ * L = min(remaining, floor(w/4)) bytes (Section VI step 5: size(B)*4 <=
+ * size(A)); bit pair i (bits 2i+1..2i) of the row's data byte j goes to the
+ * low two bits of plane pixel L*i + j of that row.  No length header: the
+ * caller passes `len`, as the paper's extract call passes N.
+ *
+ * lsb_paper_capacity: h * floor(w/4) bytes.  Host-only.
+ * lsb_paper_embed: stego = cover with the data placed as above; every other
+ *   byte copied (stego == cover: in place).  LSB_E_CAPACITY if len exceeds
+ *   the capacity, LSB_E_ARG if plane >= c or buffers overlap otherwise.
+ * lsb_paper_extract: data_out[0..len) from the stego image (data_out's
+ *   bytes are all written).
+ */
+int64_t lsb_paper_capacity(uint32_t h, uint32_t w);
+int lsb_paper_embed(const uint8_t *cover, uint8_t *stego, uint32_t h,
+                    uint32_t w, uint32_t c, uint32_t plane,
+                    const uint8_t *data, uint64_t len, void *stream);
+int lsb_paper_extract(const uint8_t *stego, uint32_t h, uint32_t w,
+                      uint32_t c, uint32_t plane, uint8_t *data_out,
+                      uint64_t len, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched form: thousands of covers of uneven size and k in one persistent
  * launch (the paper's per-row loop over an image, Section VI steps 4-5, and
  * its frame loop over a video, generalised to independent covers).

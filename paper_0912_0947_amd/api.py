@@ -13,6 +13,7 @@ import torch
 from ._lib import (E_ARG, OK, OP_EMBED, OP_EXTRACT, LaunchCfg, LsbError, check, lib)
 
 __all__ = ["capacity", "embed", "extract", "extract_sync", "embed_raw", "extract_raw",
+           "paper_capacity", "paper_embed", "paper_extract",
            "tune_get", "tune_set", "autotune", "LsbError", "OK", "OP_EMBED", "OP_EXTRACT"]
 
 
@@ -100,6 +101,35 @@ def extract_raw(stego: torch.Tensor, t0: int, stream_out: torch.Tensor, stream_b
     check(lib().lsb_extract_raw(_u8(stego, "stego"), stego.numel(), t0, _u8(stream_out, "stream_out"),
                                 stream_bits, k, _stream_ptr(stream)))
     return stream_out
+
+
+def paper_capacity(h: int, w: int) -> int:
+    """h * floor(w/4): data bytes the paper's layout holds in one plane."""
+    return int(lib().lsb_paper_capacity(h, w))
+
+
+def paper_embed(cover: torch.Tensor, h: int, w: int, c: int, plane: int, data: torch.Tensor,
+                out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """The paper's own layout: 2 bits per byte in one plane, greedy rows,
+    bit pair i of data byte j in pixel L*i + j.  ``out`` may be ``cover``."""
+    if cover.numel() != h * w * c:
+        raise ValueError("cover must hold h*w*c bytes")
+    stego = torch.empty_like(cover) if out is None else out
+    check(lib().lsb_paper_embed(_u8(cover, "cover"), _u8(stego, "out"), h, w, c, plane, _u8(data, "data"),
+                                data.numel(), _stream_ptr(stream)))
+    return stego
+
+
+def paper_extract(stego: torch.Tensor, h: int, w: int, c: int, plane: int, length: int,
+                  out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Inverse of paper_embed for ``length`` data bytes."""
+    if stego.numel() != h * w * c:
+        raise ValueError("stego must hold h*w*c bytes")
+    if out is None:
+        out = torch.empty(length, dtype=torch.uint8, device=stego.device)
+    check(lib().lsb_paper_extract(_u8(stego, "stego"), h, w, c, plane, _u8(out, "out") if length else None,
+                                  length, _stream_ptr(stream)))
+    return out
 
 
 def tune_get(op: int, k: int, n: int) -> dict:

@@ -1,0 +1,161 @@
+// lsb_paper_device.hpp -- device code of the paper's own layout
+// (arXiv:0912.0947, Section VI steps 2-7, Section VII steps 2-6): 2 bits per
+// byte in one colour plane, greedy per-row data chunks, bit pair i of data
+// byte j in plane pixel L*i + j.  Included by lsb_paper.hip.
+#pragma once
+
+#include "lsb_device.hpp"
+
+namespace lsb {
+
+struct PaperSpan {
+    const uint8_t *src;
+    uint8_t *dst;
+    const uint8_t *data;
+    uint8_t *out;
+    uint64_t n;         // h * w * c
+    uint64_t len;       // data bytes
+    uint64_t rowbytes;  // w * c
+    uint32_t w, c, plane, q;  // q = w / 4 data bytes per full row
+    int inplace;
+};
+
+// New value of the plane byte at row y, pixel x (Section VI step 7: clear
+// the low two bits, OR in bits 2i+1..2i of data byte j, with x = L*i + j).
+__device__ __forceinline__ uint32_t paper_pixel(const PaperSpan &p, uint64_t y, uint32_t x, uint32_t byte) {
+    const uint64_t first = y * p.q;  // first data byte of row y
+    if (first >= p.len) return byte;
+    const uint64_t left = p.len - first;
+    const uint32_t L = left < p.q ? (uint32_t)left : p.q;
+    if (x >= 4 * L) return byte;
+    const uint32_t i = (x >= L) + (x >= 2 * L) + (x >= 3 * L);
+    const uint32_t j = x - i * L;
+    const uint32_t d = p.data[first + j];
+    return (byte & 0xFCu) | ((d >> (2 * i)) & 3u);
+}
+
+// Bytes [t, t_end) of one row-ordered run, with (y, x, ch) the position of t.
+// Walks positions by increments; applies paper_pixel to plane bytes.
+__device__ __forceinline__ void paper_walk_bytes(const PaperSpan &p, uint64_t t, uint64_t t_end, uint8_t *bytes) {
+    uint64_t y = t / p.rowbytes;
+    const uint64_t rem = t - y * p.rowbytes;
+    uint32_t x = (uint32_t)(rem / p.c);
+    uint32_t ch = (uint32_t)(rem - (uint64_t)x * p.c);
+    for (uint64_t k = 0; t + k < t_end; ++k) {
+        if (ch == p.plane) bytes[k] = (uint8_t)paper_pixel(p, y, x, bytes[k]);
+        if (++ch == p.c) {
+            ch = 0;
+            if (++x == p.w) {
+                x = 0;
+                ++y;
+            }
+        }
+    }
+}
+
+// One 16-byte vector starting at cover byte t, for rows of at least 16
+// bytes (so the vector touches at most two rows).  Positions advance by
+// selects, all data-byte gathers of the vector are issued together, then the
+// plane bytes of carrying rows are updated (Section VI step 7).
+__device__ __forceinline__ u32x4 paper_vec16(const PaperSpan &p, uint64_t t, u32x4 v) {
+    const uint64_t y = t / p.rowbytes;
+    const uint32_t rem = (uint32_t)(t - y * p.rowbytes);
+    uint32_t x = rem / p.c;
+    uint32_t ch = rem - x * p.c;
+    // data chunk of row y and of row y + 1
+    uint64_t first[2];
+    uint32_t L[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        first[r] = (y + r) * p.q;
+        const uint64_t left = first[r] < p.len ? p.len - first[r] : 0;
+        L[r] = left < p.q ? (uint32_t)left : p.q;
+    }
+    uint32_t row = 0;
+    bool need[16];
+    uint32_t pair[16];
+    uint64_t at[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const uint32_t Lr = row ? L[1] : L[0];
+        need[k] = ch == p.plane && x < 4 * Lr;
+        const uint32_t i = (x >= Lr) + (x >= 2 * Lr) + (x >= 3 * Lr);
+        pair[k] = 2 * i;
+        at[k] = (row ? first[1] : first[0]) + (x - i * Lr);
+        // advance to the next byte: channel, then pixel, then row
+        const bool ch_wrap = ch + 1 == p.c;
+        const bool x_wrap = ch_wrap && x + 1 == p.w;
+        ch = ch_wrap ? 0 : ch + 1;
+        x = x_wrap ? 0 : (ch_wrap ? x + 1 : x);
+        row = x_wrap ? 1 : row;
+    }
+    uint32_t d[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) d[k] = need[k] ? p.data[at[k]] : 0u;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (need[k]) {
+            const int sh = 8 * (k & 3);
+            const uint32_t val = (d[k] >> pair[k]) & 3u;
+            v[k >> 2] = (v[k >> 2] & ~(3u << sh)) | (val << sh);
+        }
+    }
+    return v;
+}
+
+// Embed: every cover byte is read once and written once (16 bytes per lane
+// when both pointers are 16-byte aligned and rows hold at least 16 bytes,
+// else one byte per lane).
+template <bool VEC>
+__global__ void __launch_bounds__(256) lsb_paper_embed_kernel(PaperSpan p) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t rows_with_data = p.q ? ceil_div(p.len, p.q) : 0;
+    const uint64_t data_end = rows_with_data * p.rowbytes;  // bytes past it never change
+    if constexpr (VEC) {
+        const uint64_t vecs = ceil_div(p.n, 16);
+        for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < vecs; u += stride) {
+            const uint64_t t = 16 * u;
+            if (t + 16 <= p.n) {
+                u32x4 v = load16<true>(p.src + t);
+                if (t >= data_end) {  // no data in this vector's rows
+                    if (!p.inplace) store16<true>(p.dst + t, v);
+                    continue;
+                }
+                store16<true>(p.dst + t, paper_vec16(p, t, v));
+            } else {
+                uint8_t b[16];
+                const uint64_t m = p.n - t;
+                for (uint64_t k = 0; k < m; ++k) b[k] = p.src[t + k];
+                paper_walk_bytes(p, t, p.n, b);
+                for (uint64_t k = 0; k < m; ++k) p.dst[t + k] = b[k];
+            }
+        }
+    } else {
+        for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < p.n; t += stride) {
+            uint8_t b = p.src[t];
+            if (t < data_end) paper_walk_bytes(p, t, t + 1, &b);
+            if (!p.inplace || t < data_end) p.dst[t] = b;
+        }
+    }
+}
+
+// Extract: one lane per data byte d; row y = d / q holds bytes
+// [y*q, y*q + L); byte j of the row is ORed together from the low two bits
+// of pixels L*i + j, shifted left by 2i (Section VII step 6).
+__global__ void __launch_bounds__(256) lsb_paper_extract_kernel(PaperSpan p) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t d = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; d < p.len; d += stride) {
+        const uint64_t y = d / p.q;
+        const uint64_t first = y * p.q;
+        const uint32_t j = (uint32_t)(d - first);
+        const uint64_t left = p.len - first;
+        const uint32_t L = left < p.q ? (uint32_t)left : p.q;
+        const uint8_t *row = p.src + y * p.rowbytes + p.plane;
+        uint32_t v = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) v |= ((uint32_t)row[(uint64_t)(L * i + j) * p.c] & 3u) << (2 * i);
+        p.out[d] = (uint8_t)v;
+    }
+}
+
+}  // namespace lsb
