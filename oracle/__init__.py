@@ -47,7 +47,7 @@ def build(force: bool = False) -> str:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(
             ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared",
-             "-o", tmp, _SRC])
+             "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -80,6 +80,16 @@ def _bind(path: str):
     lib.oracle_paper_extract.restype = ctypes.c_int
     lib.oracle_paper_extract.argtypes = [u8p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                          ctypes.c_uint32, u8p, ctypes.c_uint64]
+    lib.oracle_embed_plane.restype = ctypes.c_int
+    lib.oracle_embed_plane.argtypes = [u8p, u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, u8p,
+                                       ctypes.c_uint32, ctypes.c_int]
+    lib.oracle_extract_plane.restype = ctypes.c_int
+    lib.oracle_extract_plane.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                         u8p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32)]
+    lib.oracle_sse.restype = ctypes.c_uint64
+    lib.oracle_sse.argtypes = [u8p, u8p, ctypes.c_uint64]
+    lib.oracle_psnr.restype = ctypes.c_double
+    lib.oracle_psnr.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     return lib
 
 
@@ -189,3 +199,35 @@ def paper_extract(stego, h: int, w: int, c: int, plane: int, length: int):
     out = np.zeros(max(length, 1), dtype=np.uint8)
     rc = _load().oracle_paper_extract(_ptr(stego), h, w, c, plane, _ptr(out), length)
     return rc, out[:length]
+
+
+# ---------------------------------------------------------------------------
+# One colour plane with the general method; squared error and PSNR.
+def embed_plane(cover, c: int, plane: int, msg, k: int):
+    cover = _u8(cover)
+    msg = _u8(msg)
+    stego = cover.copy()
+    rc = _load().oracle_embed_plane(_ptr(cover), _ptr(stego), cover.size // c, c, plane, _ptr(msg), msg.size, k)
+    return rc, stego
+
+
+def extract_plane(stego, c: int, plane: int, k: int, out_cap: int | None = None):
+    stego = _u8(stego)
+    pixels = stego.size // c
+    if out_cap is None:
+        out_cap = max(capacity(pixels, k), 0)
+    out = np.zeros(max(out_cap, 1), dtype=np.uint8)
+    ln = ctypes.c_uint32(0)
+    rc = _load().oracle_extract_plane(_ptr(stego), pixels, c, plane, k, _ptr(out), out_cap, ctypes.byref(ln))
+    return rc, int(ln.value), (out[: ln.value].copy() if rc == OK else None)
+
+
+def sse(a, b) -> int:
+    a = _u8(a)
+    b = _u8(b)
+    assert a.size == b.size
+    return int(_load().oracle_sse(_ptr(a), _ptr(b), a.size))
+
+
+def psnr(sse_value: int, count: int) -> float:
+    return float(_load().oracle_psnr(sse_value, count))

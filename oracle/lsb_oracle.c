@@ -19,6 +19,7 @@
  */
 #include "lsb_oracle.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -264,4 +265,74 @@ int oracle_paper_extract(const uint8_t *stego, uint32_t h, uint32_t w,
         remaining -= L;
     }
     return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * One colour plane with the general method: gather the plane (Section VI
+ * step 2), run the plain definition on it, scatter it back.
+ */
+int oracle_embed_plane(const uint8_t *cover, uint8_t *stego, uint64_t pixels,
+                       uint32_t c, uint32_t plane, const uint8_t *msg,
+                       uint32_t len, int k)
+{
+    if (c == 0 || plane >= c || (pixels > 0 && (!cover || !stego)))
+        return ORACLE_E_ARG;
+    int64_t cap = oracle_capacity(pixels, k);
+    if (cap < 0)
+        return (int)cap;
+    if ((uint64_t)len > (uint64_t)cap)
+        return ORACLE_E_CAPACITY;
+    uint8_t *a = (uint8_t *)malloc(pixels ? (size_t)pixels : 1);
+    uint8_t *b = (uint8_t *)malloc(pixels ? (size_t)pixels : 1);
+    if (!a || !b) {
+        free(a);
+        free(b);
+        return ORACLE_E_NOMEM;
+    }
+    for (uint64_t p = 0; p < pixels; ++p)
+        a[p] = cover[p * c + plane];
+    int rc = oracle_embed(a, b, pixels, msg, len, k);
+    if (rc == ORACLE_OK) {
+        if (stego != cover)
+            memcpy(stego, cover, (size_t)(pixels * c));
+        for (uint64_t p = 0; p < pixels; ++p)
+            stego[p * c + plane] = b[p];
+    }
+    free(a);
+    free(b);
+    return rc;
+}
+
+int oracle_extract_plane(const uint8_t *stego, uint64_t pixels, uint32_t c,
+                         uint32_t plane, int k, uint8_t *msg_out,
+                         uint64_t out_cap, uint32_t *len_out)
+{
+    if (c == 0 || plane >= c || !len_out || (pixels > 0 && !stego))
+        return ORACLE_E_ARG;
+    uint8_t *a = (uint8_t *)malloc(pixels ? (size_t)pixels : 1);
+    if (!a)
+        return ORACLE_E_NOMEM;
+    for (uint64_t p = 0; p < pixels; ++p)
+        a[p] = stego[p * c + plane];
+    int rc = oracle_extract(a, pixels, k, msg_out, out_cap, len_out);
+    free(a);
+    return rc;
+}
+
+uint64_t oracle_sse(const uint8_t *a, const uint8_t *b, uint64_t n)
+{
+    uint64_t sum = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        int64_t d = (int64_t)a[i] - (int64_t)b[i];
+        sum += (uint64_t)(d * d);
+    }
+    return sum;
+}
+
+double oracle_psnr(uint64_t sse, uint64_t count)
+{
+    if (sse == 0 || count == 0)
+        return INFINITY;
+    double mse = (double)sse / (double)count;
+    return 10.0 * log10(255.0 * 255.0 / mse);
 }

@@ -90,6 +90,23 @@ int oracle_paper_extract(const uint8_t *stego, uint32_t h, uint32_t w,
                          uint32_t c, uint32_t plane, uint8_t *data,
                          uint64_t len);
 
+/* ---------------------------------------------------------------------
+ * One colour plane (Section VI step 2, Section VII step 2) with the general
+ * method: the fields are the bytes of plane `plane` of an image of
+ * `pixels` pixels x c channels (HWC), in raster order; everything else as
+ * oracle_embed / oracle_extract.  Bytes of the other planes are copied. */
+int oracle_embed_plane(const uint8_t *cover, uint8_t *stego, uint64_t pixels,
+                       uint32_t c, uint32_t plane, const uint8_t *msg,
+                       uint32_t len, int k);
+int oracle_extract_plane(const uint8_t *stego, uint64_t pixels, uint32_t c,
+                         uint32_t plane, int k, uint8_t *msg_out,
+                         uint64_t out_cap, uint32_t *len_out);
+
+/* Sum of squared differences of two byte strings (Section VIII reports the
+ * peak signal-to-noise ratio 10*log10(255^2 / MSE), MSE = SSE / count). */
+uint64_t oracle_sse(const uint8_t *a, const uint8_t *b, uint64_t n);
+double oracle_psnr(uint64_t sse, uint64_t count);
+
 #ifdef __cplusplus
 }
 #endif

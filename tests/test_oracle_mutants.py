@@ -36,6 +36,9 @@ MUTANTS = {
                               "uint64_t L = w / 4 < remaining ? w / 4 : remaining; if (y % 2) L = remaining < 1 ? remaining : 1;"),
     "paper_wrong_plane": ("return ((uint64_t)y * w + x) * c + plane;", "return ((uint64_t)y * w + x) * c;"),
     "paper_extract_no_shift": ("                v <<= 2 * i;\n", "                v <<= 0;\n"),
+    "sse_abs_not_square": ("sum += (uint64_t)(d * d);", "sum += (uint64_t)(d < 0 ? -d : d);"),
+    "psnr_peak_not_squared": ("return 10.0 * log10(255.0 * 255.0 / mse);", "return 10.0 * log10(255.0 / mse);"),
+    "plane_index_dropped": ("        a[p] = cover[p * c + plane];\n", "        a[p] = cover[p * c];\n"),
     "buffer_check_missing": ("if ((uint64_t)len > out_cap)\n        return ORACLE_E_BUFFER;", "if (0)\n        return ORACLE_E_BUFFER;"),
 }
 
@@ -50,10 +53,11 @@ def test_mutant_is_caught(name, tmp_path):
     lib = tmp_path / "libmutant.so"
     subprocess.check_call(["gcc", "-O1", "-std=c99", "-fPIC", "-shared",
                            "-I", os.path.join(ROOT, "oracle"),
-                           "-o", str(lib), str(mutant_c)])
+                           "-o", str(lib), str(mutant_c), "-lm"])
     env = dict(os.environ, LSB_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_paper.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_paper.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_plane_psnr.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "mutant %s survived every pin:\n%s" % (name, r.stdout[-2000:])
