@@ -196,6 +196,119 @@ def bench_paper_layout(api, lib_handle, cover, dev, reps=5):
     return res
 
 
+def bench_quality(api, lib_handle, cover, stego_by_k, dev, reps=5):
+    """Section VIII's quality figure on the large image: PSNR of each stego
+    against its cover over all bytes, from the device squared-error kernel
+    (algorithmic bytes 2n per launch), and single-plane embedding at the
+    paper's 2 bits per byte (plane 0, full plane capacity)."""
+    import torch
+
+    from paper_0912_0947_amd import inputs
+
+    n = cover.numel()
+    out = {}
+    for k, st in stego_by_k.items():
+        sse = int(api.sse(st, cover).cpu().item())
+        out["psnr_db_k%d" % k] = round(api.psnr(sse, n), 4)
+    sse_buf = torch.empty(1, dtype=torch.int64, device=dev)
+    ms = []
+    for r in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        e1.record()
+        torch.cuda.synchronize()
+        lib_handle.lsb_time_next_launch(e0, e1)
+        api.sse(stego_by_k[1], cover, out=sse_buf)
+        torch.cuda.synchronize()
+        if r:
+            ms.append(e0.elapsed_time(e1))
+    us = sorted(ms)[len(ms) // 2] * 1e3
+    out["sse_kernel"] = {"bytes": 2 * n, "us_median": round(us, 2), "GBps": round(2 * n / (us * 1e-6) / 1e9, 1)}
+    pixels = n // 3
+    msg = torch.empty(api.capacity(pixels, 2), dtype=torch.uint8, device=dev)
+    inputs.fill_uniform(msg, 1701)
+    plane_st = torch.empty_like(cover)
+    api.embed_plane(cover, 3, 0, msg, 2, out=plane_st)
+    sse = int(api.sse(plane_st, cover).cpu().item())
+    out["plane0_k2"] = {"psnr_db_plane": round(api.psnr(sse, pixels), 4), "psnr_db_all_bytes": round(api.psnr(sse, n), 4),
+                        "message_bytes": msg.numel()}
+    ms = []
+    for r in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        e1.record()
+        torch.cuda.synchronize()
+        lib_handle.lsb_time_next_launch(e0, e1)
+        api.embed_plane(plane_st, 3, 0, msg, 2, out=plane_st)  # in place: the strided kernel alone
+        torch.cuda.synchronize()
+        if r:
+            ms.append(e0.elapsed_time(e1))
+    us = sorted(ms)[len(ms) // 2] * 1e3
+    b = 2 * pixels + 4 + msg.numel()
+    out["plane0_k2"]["inplace_embed"] = {"bytes": b, "us_median": round(us, 2), "GBps": round(b / (us * 1e-6) / 1e9, 1)}
+    return out
+
+
+def bench_video(api, lib_handle, dev, log_fn, frames=600, h=1080, w=1920):
+    """Video workload: 600 frames of 1080x1920x3 (3.73 GB) carrying one
+    stream at k = 1 and 50 % capacity (|S| = 233,280,000 bytes).
+    device-resident whole clip: one lsb_embed launch over the clip;
+    device-resident per frame: 600 lsb_embed_raw launches (t0 = f * frame);
+    host-streamed: the clip in pinned host memory pipelined through a 4-slot
+    device ring (copy in / embed / copy out on three streams), whose rate is
+    bounded by PCIe, not HBM."""
+    import torch
+
+    from paper_0912_0947_amd import inputs
+
+    fb = h * w * 3
+    clip = inputs.video_frames(frames, h, w, device=dev).view(-1)
+    n = clip.numel()
+    ln = n // 8 // 2 - 4
+    msg = torch.empty(ln, dtype=torch.uint8, device=dev)
+    inputs.fill_uniform(msg, 303)
+    stego = torch.empty_like(clip)
+    res = {"workload": "%d frames %dx%dx3 (%d B), k=1, |S| = %d B" % (frames, h, w, n, ln + 4)}
+
+    def timed(fn, reps=3):
+        best = 1e9
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best
+
+    t = timed(lambda: api.embed(clip, msg, 1, out=stego))
+    res["device_whole_clip"] = {"bytes": 2 * n + ln + 4, "ms": round(t * 1e3, 3), "GBps": round((2 * n + ln + 4) / t / 1e9, 1)}
+    stream = torch.empty(ln + 4, dtype=torch.uint8, device=dev)
+    stream[:4] = torch.tensor(list(int(ln).to_bytes(4, "big")), dtype=torch.uint8)
+    stream[4:] = msg
+    per = torch.empty_like(clip)
+
+    def per_frame():
+        for f in range(frames):
+            api.embed_raw(clip[f * fb:(f + 1) * fb], f * fb, stream, 8 * (ln + 4), 1, out=per[f * fb:(f + 1) * fb])
+
+    t = timed(per_frame)
+    res["device_per_frame"] = {"launches": frames, "ms": round(t * 1e3, 3), "GBps": round((2 * n + ln + 4) / t / 1e9, 1)}
+    assert torch.equal(per, stego), "per-frame and whole-clip embeds differ"
+    host = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    host.copy_(clip)
+    host_out = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    ring = torch.empty(4 * fb, dtype=torch.uint8, device=dev)
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    t = timed(lambda: api.video_embed_host(host, host_out, fb, stream, 8 * (ln + 4), 1, ring, streams), reps=2)
+    res["host_streamed"] = {"ring_slots": 4, "ms": round(t * 1e3, 3), "frames_per_s": round(frames / t, 1),
+                            "pcie_GBps_each_way": round(n / t / 1e9, 1)}
+    check = torch.equal(host_out[:fb * 8].to(dev), stego[:fb * 8]) and torch.equal(host_out[-fb:].to(dev), stego[-fb:])
+    assert check, "host-streamed frames differ"
+    log_fn("video: %s" % res)
+    del clip, stego, per, host, host_out, ring
+    return res
+
+
 def bench_serving(api, serve, dev, pool, log_fn, rates=(2000.0, 10000.0, 50000.0), seconds=1.0,
                   budget=64 << 30):
     """Open-loop Poisson request streams over the device-resident 4096-cover
@@ -371,11 +484,15 @@ def main():
         "copy_reference": copy_ref,
     }
     result["paper_layout"] = bench_paper_layout(api, L, covers[0], dev)
+    result["quality"] = bench_quality(api, L, covers[0], {k: stegos[k][1] for k in KS}, dev)
 
     if not args.no_batched:
         from paper_0912_0947_amd import batch, serve
 
         del covers, stegos, outs
+        torch.cuda.empty_cache()
+        log("video (600 x 1080p) ...")
+        result["video"] = bench_video(api, L, dev, log)
         torch.cuda.empty_cache()
         log("batched (4096 uneven covers) ...")
         result["batched"], pool = bench_batched(api, batch, dev, log)

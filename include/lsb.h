@@ -135,6 +135,45 @@ int lsb_paper_extract(const uint8_t *stego, uint32_t h, uint32_t w,
                       uint64_t len, void *stream);
 
 /* ------------------------------------------------------------------------
+ * One colour plane with the general method (the paper separates one plane
+ * before embedding, Section VI step 2 / Section VII step 2): the fields are
+ * the bytes p*c + plane of an HWC image of `pixels` pixels, in raster order;
+ * stream, header, bit order and errors as lsb_embed / lsb_extract, with the
+ * capacity lsb_capacity(pixels, k).  lsb_embed_plane copies the other bytes
+ * (stego == cover: in place, only plane bytes are rewritten).
+ */
+int lsb_embed_plane(const uint8_t *cover, uint8_t *stego, uint64_t pixels,
+                    uint32_t c, uint32_t plane, const uint8_t *msg,
+                    uint32_t len, int k, void *stream);
+int lsb_extract_plane(const uint8_t *stego, uint64_t pixels, uint32_t c,
+                      uint32_t plane, int k, uint8_t *msg_out,
+                      uint64_t out_cap, uint32_t *len_out_dev,
+                      int32_t *status_out_dev, void *stream);
+
+/* Sum over i < n of (a[i] - b[i])^2 into the device word *sse_dev (which
+ * the call overwrites).  The paper's quality figure (Section VIII) is
+ * PSNR = 10*log10(255^2 * count / sse), with count the bytes the mean is
+ * taken over (all bytes of the cover). */
+int lsb_sse(const uint8_t *a, const uint8_t *b, uint64_t n, uint64_t *sse_dev,
+            void *stream);
+
+/* ------------------------------------------------------------------------
+ * Host-streamed video (the paper's copy-in / launch / copy-out flow of
+ * Sections III and V, pipelined): `frames` frames of `frame_bytes` bytes in
+ * pinned host memory are copied to a ring of `ring_slots` device slots
+ * (dev_ring holds ring_slots * frame_bytes bytes), embedded in place as raw
+ * slices t0 = f * frame_bytes of one logical stream (stream_dev, a device
+ * buffer of stream_bits bits), and copied back to host_stego, on three
+ * distinct streams (copy in, compute, copy out) ordered by events.  Returns
+ * after enqueueing; host_stego is complete once s_out has drained.
+ */
+int lsb_video_embed_host(const uint8_t *host_frames, uint8_t *host_stego,
+                         uint64_t frame_bytes, uint64_t frames,
+                         const uint8_t *stream_dev, uint64_t stream_bits,
+                         int k, uint8_t *dev_ring, uint32_t ring_slots,
+                         void *s_in, void *s_compute, void *s_out);
+
+/* ------------------------------------------------------------------------
  * Batched form: thousands of covers of uneven size and k in one persistent
  * launch (the paper's per-row loop over an image, Section VI steps 4-5, and
  * its frame loop over a video, generalised to independent covers).

@@ -13,7 +13,8 @@ import torch
 from ._lib import (E_ARG, OK, OP_EMBED, OP_EXTRACT, LaunchCfg, LsbError, check, lib)
 
 __all__ = ["capacity", "embed", "extract", "extract_sync", "embed_raw", "extract_raw",
-           "paper_capacity", "paper_embed", "paper_extract",
+           "paper_capacity", "paper_embed", "paper_extract", "embed_plane", "extract_plane", "sse", "psnr",
+           "video_embed_host",
            "tune_get", "tune_set", "autotune", "LsbError", "OK", "OP_EMBED", "OP_EXTRACT"]
 
 
@@ -130,6 +131,71 @@ def paper_extract(stego: torch.Tensor, h: int, w: int, c: int, plane: int, lengt
     check(lib().lsb_paper_extract(_u8(stego, "stego"), h, w, c, plane, _u8(out, "out") if length else None,
                                   length, _stream_ptr(stream)))
     return out
+
+
+def embed_plane(cover: torch.Tensor, c: int, plane: int, msg: torch.Tensor, k: int,
+                out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """General method on one colour plane of an HWC image (fields = bytes
+    p*c + plane); other planes copied.  ``out`` may be ``cover``."""
+    if cover.numel() % c:
+        raise ValueError("cover bytes must be a multiple of the channel count")
+    stego = torch.empty_like(cover) if out is None else out
+    check(lib().lsb_embed_plane(_u8(cover, "cover"), _u8(stego, "out"), cover.numel() // c, c, plane,
+                                _u8(msg, "msg"), msg.numel(), k, _stream_ptr(stream)))
+    return stego
+
+
+def extract_plane(stego: torch.Tensor, c: int, plane: int, k: int, out: torch.Tensor | None = None,
+                  len_status: torch.Tensor | None = None, stream=None):
+    """Asynchronous single-plane extract; returns (out, len_status) like extract."""
+    pixels = stego.numel() // c
+    if out is None:
+        cap = lib().lsb_capacity(pixels, k)
+        out = torch.empty(max(int(cap), 0), dtype=torch.uint8, device=stego.device)
+    if len_status is None:
+        len_status = torch.empty(2, dtype=torch.int32, device=stego.device)
+    base = len_status.data_ptr()
+    check(lib().lsb_extract_plane(_u8(stego, "stego"), pixels, c, plane, k, _u8(out, "out") if out.numel() else None,
+                                  out.numel(), ctypes.c_void_p(base), ctypes.c_void_p(base + 4),
+                                  _stream_ptr(stream)))
+    return out, len_status
+
+
+def sse(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Sum of squared byte differences as an int64 device tensor of 1 element."""
+    if a.numel() != b.numel():
+        raise ValueError("a and b must have the same size")
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=a.device)
+    check(lib().lsb_sse(_u8(a, "a"), _u8(b, "b"), a.numel(), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def psnr(sse_value: int, count: int) -> float:
+    """10*log10(255^2 / (sse / count)) in dB (host arithmetic on a reduced value)."""
+    import math
+    return math.inf if sse_value == 0 else 10.0 * math.log10(255.0 * 255.0 * count / sse_value)
+
+
+def video_embed_host(host_frames: torch.Tensor, host_stego: torch.Tensor, frame_bytes: int,
+                     stream_bytes: torch.Tensor, stream_bits: int, k: int, ring: torch.Tensor, streams):
+    """Pipeline frames from pinned host memory through the device ring:
+    copy in, embed in place (raw slice t0 = f * frame_bytes), copy out, on the
+    three streams ``streams`` = (copy in, compute, copy out).  Returns after
+    enqueueing; synchronize the third stream before reading host_stego."""
+    for t, name in ((host_frames, "host_frames"), (host_stego, "host_stego")):
+        if t.is_cuda or not t.is_pinned() or t.dtype != torch.uint8 or not t.is_contiguous():
+            raise TypeError("%s must be a contiguous pinned uint8 host tensor" % name)
+    if host_frames.numel() % frame_bytes or host_stego.numel() != host_frames.numel():
+        raise ValueError("host buffers must hold whole frames, stego as many bytes as frames")
+    slots = ring.numel() // frame_bytes
+    if slots < 1:
+        raise ValueError("ring must hold at least one frame")
+    s_in, s_c, s_out = streams
+    check(lib().lsb_video_embed_host(ctypes.c_void_p(host_frames.data_ptr()), ctypes.c_void_p(host_stego.data_ptr()),
+                                     frame_bytes, host_frames.numel() // frame_bytes, _u8(stream_bytes, "stream_bytes"),
+                                     stream_bits, k, _u8(ring, "ring"), slots, ctypes.c_void_p(s_in.cuda_stream),
+                                     ctypes.c_void_p(s_c.cuda_stream), ctypes.c_void_p(s_out.cuda_stream)))
 
 
 def tune_get(op: int, k: int, n: int) -> dict:

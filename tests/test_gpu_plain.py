@@ -276,3 +276,45 @@ def test_config3_video_full_clip():
         rc, want = oracle.embed_raw(to_host(clip[sl]), f * fb, stream_np, 8 * (4 + ln), 1)
         assert rc == 0
         assert_bytes_equal(to_host(whole[sl]), want, "frame %d vs oracle" % f)
+
+
+@pytest.mark.parametrize("k", [1, 8])
+def test_cover_beyond_4gib(k):
+    """A cover of 2^32 + 4109 bytes (byte offsets past 32 bits): the stego
+    around the 2^32 boundary, at the start and at the end equals the oracle
+    run on those slices (raw slices of the same logical stream), and the
+    message comes back whole.  At k = 8 the capacity is capped at 2^32 - 1 by
+    the header width."""
+    n = (1 << 32) + 4109
+    cover = torch.empty(n, dtype=torch.uint8, device=DEV)
+    inputs.fill_uniform(cover, 1901)
+    cap = api.capacity(n, k)
+    assert cap == min((n * k) // 8 - 4, 0xFFFFFFFF)
+    ln = cap if k == 1 else (1 << 31) + 12345
+    msg = torch.empty(ln, dtype=torch.uint8, device=DEV)
+    inputs.fill_uniform(msg, 1902)
+    stego = api.embed(cover, msg, k)
+    hdr = np.frombuffer(int(ln).to_bytes(4, "big"), np.uint8)
+    bits = 8 * (4 + ln)
+    F = -(-bits // k)
+    for t0, m in [(0, 1 << 16), ((1 << 32) - 40000, 80000), (F - 50000, 100000), (n - 70000, 70000)]:
+        t0 = max(0, min(t0, n - m))
+        # the stream bytes this slice needs, as a slice of the logical stream S
+        s_first = (k * t0) // 8
+        s_last = min((k * (t0 + m) + 7) // 8, 4 + ln)
+        s_np = np.zeros(max(s_last, 1), np.uint8)
+        if s_last > s_first:
+            lo = max(s_first, 4)
+            if s_first < 4:
+                s_np[s_first:4] = hdr[s_first:4]
+            if s_last > lo:
+                s_np[lo:s_last] = to_host(msg[lo - 4:s_last - 4])
+        rc, want = oracle.embed_raw(to_host(cover[t0:t0 + m]), t0, s_np, min(bits, 8 * s_last), k)
+        assert rc == 0
+        if 8 * s_last < bits and k * (t0 + m) > 8 * s_last:
+            want = want[: (8 * s_last) // k]  # compare only fields fully covered by the copied stream
+        assert_bytes_equal(to_host(stego[t0:t0 + want.size]), want, "k=%d slice at %d" % (k, t0))
+    out, ls = api.extract(stego, k)
+    ls = ls.cpu().numpy()
+    assert ls[1] == OK and int(np.uint32(ls[0])) == ln
+    assert torch.equal(out[:ln], msg)

@@ -1,0 +1,34 @@
+"""Host-streamed video: frames in pinned host memory pipelined through a
+device ring give the same stego frames as embedding the clip on the device."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_0912_0947_amd import api, inputs
+
+from gpu_helpers import DEV, assert_bytes_equal, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("k,slots", [(1, 3), (2, 1), (3, 4)])
+def test_pipelined_frames_equal_device_embed(k, slots):
+    frames, h, w = 24, 48, 80
+    fb = h * w * 3
+    clip = inputs.video_frames(frames, h, w, device="cpu").view(-1).contiguous()
+    stream_bits = clip.numel() * k * 2 // 3 + 7
+    stream = inputs.random_bytes((stream_bits + 7) // 8, 1801, k)
+    host = clip.pin_memory()
+    out = torch.empty_like(host).pin_memory()
+    ring = torch.empty(slots * fb, dtype=torch.uint8, device=DEV)
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    sd = torch.from_numpy(stream).to(DEV)
+    torch.cuda.synchronize()
+    api.video_embed_host(host, out, fb, sd, stream_bits, k, ring, streams)
+    streams[2].synchronize()
+    torch.cuda.synchronize()
+    want_dev = api.embed_raw(clip.to(DEV), 0, sd, stream_bits, k)
+    assert torch.equal(out, want_dev.cpu()), "pipelined frames differ from the device embed"
+    rc, want = oracle.embed_raw(clip.numpy(), 0, stream, stream_bits, k)
+    assert_bytes_equal(out.numpy(), want, "pipelined frames vs oracle k=%d" % k)
