@@ -232,20 +232,25 @@ def bench_quality(api, lib_handle, cover, stego_by_k, dev, reps=5):
     sse = int(api.sse(plane_st, cover).cpu().item())
     out["plane0_k2"] = {"psnr_db_plane": round(api.psnr(sse, pixels), 4), "psnr_db_all_bytes": round(api.psnr(sse, n), 4),
                         "message_bytes": msg.numel()}
-    ms = []
-    for r in range(reps + 1):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        e1.record()
-        torch.cuda.synchronize()
-        lib_handle.lsb_time_next_launch(e0, e1)
-        api.embed_plane(plane_st, 3, 0, msg, 2, out=plane_st)  # in place: the strided kernel alone
-        torch.cuda.synchronize()
-        if r:
-            ms.append(e0.elapsed_time(e1))
-    us = sorted(ms)[len(ms) // 2] * 1e3
-    b = 2 * pixels + 4 + msg.numel()
-    out["plane0_k2"]["inplace_embed"] = {"bytes": b, "us_median": round(us, 2), "GBps": round(b / (us * 1e-6) / 1e9, 1)}
+    got = torch.empty_like(msg)
+    ls = torch.zeros(2, dtype=torch.int32, device=dev)
+    for name, fn, b in [("embed", lambda: api.embed_plane(cover, 3, 0, msg, 2, out=plane_st), 2 * n + 4 + msg.numel()),
+                        ("extract", lambda: api.extract_plane(plane_st, 3, 0, 2, out=got, len_status=ls),
+                         n + msg.numel())]:
+        ms = []
+        for r in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            e1.record()
+            torch.cuda.synchronize()
+            lib_handle.lsb_time_next_launch(e0, e1)
+            fn()
+            torch.cuda.synchronize()
+            if r:
+                ms.append(e0.elapsed_time(e1))
+        us = sorted(ms)[len(ms) // 2] * 1e3
+        out["plane0_k2"][name] = {"bytes": b, "us_median": round(us, 2), "GBps": round(b / (us * 1e-6) / 1e9, 1)}
+    assert torch.equal(got, msg), "single-plane round trip failed"
     return out
 
 

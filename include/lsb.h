@@ -235,6 +235,8 @@ typedef struct lsb_launch_cfg {
     int32_t unroll;         /* 16-byte vectors per lane per step: 1, 2, 4  */
     int32_t blocks_per_cu;  /* grid cap = blocks_per_cu * CUs; 0 = no cap  */
     int32_t nontemporal;    /* 1 = streaming (non-temporal) loads/stores   */
+    int32_t pack;           /* extract, k = 1: 0 = per-lane multiply pack,
+                               1 = wavefront ballots staged through LDS    */
 } lsb_launch_cfg;
 
 int lsb_tune_get(int op, int k, uint64_t n, lsb_launch_cfg *cfg);

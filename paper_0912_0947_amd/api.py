@@ -204,8 +204,9 @@ def tune_get(op: int, k: int, n: int) -> dict:
     return cfg.as_dict()
 
 
-def tune_set(op: int, k: int, bucket: int, block: int, unroll: int, blocks_per_cu: int, nontemporal: int):
-    cfg = LaunchCfg(block, unroll, blocks_per_cu, nontemporal)
+def tune_set(op: int, k: int, bucket: int, block: int, unroll: int, blocks_per_cu: int, nontemporal: int,
+             pack: int = 0):
+    cfg = LaunchCfg(block, unroll, blocks_per_cu, nontemporal, pack)
     check(lib().lsb_tune_set(op, k, bucket, ctypes.byref(cfg)))
 
 

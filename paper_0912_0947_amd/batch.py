@@ -78,7 +78,7 @@ def tune_get():
 
 
 def tune_set(block: int, unroll: int, blocks_per_cu: int, nontemporal: int, tile_vectors: int) -> None:
-    cfg = LaunchCfg(block, unroll, blocks_per_cu, nontemporal)
+    cfg = LaunchCfg(block, unroll, blocks_per_cu, nontemporal, 0)
     check(lib().lsb_batch_tune_set(ctypes.byref(cfg), int(tile_vectors)))
 
 

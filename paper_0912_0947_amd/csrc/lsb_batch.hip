@@ -166,7 +166,7 @@ static BatchFn batch_fn(int unroll, int nt) {
 
 // Batched-kernel configuration (global, read at each run).
 static std::mutex g_batch_mu;
-static lsb_launch_cfg g_batch_cfg = {256, 2, 8, 0};
+static lsb_launch_cfg g_batch_cfg = {256, 2, 8, 0, 0};
 static int64_t g_tile_vectors = 8192;
 
 }  // namespace lsb

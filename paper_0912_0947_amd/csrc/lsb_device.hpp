@@ -395,14 +395,51 @@ __device__ __forceinline__ void extract_store_group(const Span &s, uintptr_t out
     }
 }
 
+// Same for k = 1 with wavefront ballots.  The wave's 1 KiB of stego bytes
+// per vector set is staged in LDS so that lane L can read bytes L, L+64, ...,
+// L+960; ballot m over their LSBs then holds 64 consecutive stream bits
+// (bit L = stream bit 64m + L), i.e. 8 output bytes, which a per-byte bit
+// reversal puts in MSB-first order.  Lanes 0..15 store the 16 ballots.
+// `stage` is this wave's 1 KiB of LDS.  Must be called by all 64 lanes.
+template <int UNR>
+__device__ __forceinline__ void extract_store_group_ballot(const Span &s, uintptr_t out_base, uint64_t u0,
+                                                           const u32x4 *c, uint32_t lane, uint8_t *stage) {
+#pragma unroll
+    for (int j = 0; j < UNR; ++j) {
+        *reinterpret_cast<u32x4 *>(stage + 16 * lane) = c[j];
+        uint32_t bits = 0;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) bits |= ((uint32_t)stage[lane + 64 * m] & 1u) << m;
+        uint64_t mine = 0;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const uint64_t mask = __ballot((bits >> m) & 1u);
+            mine = lane == (uint32_t)m ? mask : mine;
+        }
+        if (lane < 16) {
+            const uint64_t v = __builtin_bswap64(__builtin_bitreverse64(mine));
+            uint8_t *p = reinterpret_cast<uint8_t *>(out_base + 2 * (u0 + (uint64_t)j * 64) + 8 * lane);
+            if (s.words) {
+                reinterpret_cast<uint32_t *>(p)[0] = (uint32_t)v;
+                reinterpret_cast<uint32_t *>(p)[1] = (uint32_t)(v >> 32);
+            } else {
+#pragma unroll
+                for (int b = 0; b < 8; ++b) p[b] = (uint8_t)(v >> (8 * b));
+            }
+        }
+    }
+}
+
 __host__ __device__ inline uintptr_t extract_out_base(const Span &s) {
     return (uintptr_t)s.out + stream_byte0(s) - s.hdr_len;
 }
 
-template <int K, int UNR, bool NT>
+// BALLOT (k = 1 only): pack fast groups with wavefront ballots through the
+// wave's 1 KiB LDS `stage` instead of per-lane multiplies.
+template <int K, int UNR, bool NT, bool BALLOT = false>
 __device__ __forceinline__ void extract_walk(const Span &s, const Ranges &r, uint64_t v_begin,
                                              uint64_t v_end, uint64_t wave, uint64_t n_waves,
-                                             uint32_t lane) {
+                                             uint32_t lane, uint8_t *stage = nullptr) {
     constexpr uint64_t G = 64 * UNR;
     const uint64_t sb = stream_byte0(s);
     const uintptr_t out_base = extract_out_base(s);
@@ -413,7 +450,10 @@ __device__ __forceinline__ void extract_walk(const Span &s, const Ranges &r, uin
 #pragma unroll
             for (int j = 0; j < UNR; ++j)
                 c[j] = load16<NT>(s.src + 16 * (u0 + (uint64_t)j * 64 + lane));
-            extract_store_group<K, UNR>(s, out_base, u0, c, lane);
+            if constexpr (BALLOT && K == 1)
+                extract_store_group_ballot<UNR>(s, out_base, u0, c, lane, stage);
+            else
+                extract_store_group<K, UNR>(s, out_base, u0, c, lane);
         } else {
             for (int j = 0; j < UNR; ++j) {
                 const uint64_t u = u0 + (uint64_t)j * 64 + lane;

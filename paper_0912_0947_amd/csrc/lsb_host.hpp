@@ -22,6 +22,7 @@ int hip_fail(hipError_t e, const char *what);
 // Events set by lsb_time_next_launch for the calling thread; returns them
 // and clears the request (both null when none is pending).
 void take_launch_events(hipEvent_t *start, hipEvent_t *stop);
+int set_launch_events(void *start, void *stop);
 
 // Compute units of the current device (cached per device).
 int device_cus();

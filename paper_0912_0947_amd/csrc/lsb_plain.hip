@@ -36,16 +36,19 @@ __global__ void __launch_bounds__(1024) lsb_embed_kernel(Span s) {
 // Vector extract.  header != 0: decode the length on the device, report it
 // and the status through block 0, and extract the message; header == 0: raw
 // slice, s.bits already holds the end bit.
-template <int K, int UNR, bool NT>
+template <int K, int UNR, bool NT, bool BALLOT>
 __global__ void __launch_bounds__(1024)
     lsb_extract_kernel(Span s, int header, uint64_t out_cap, uint32_t *len_out, int32_t *status_out) {
     constexpr uint64_t G = 64 * UNR;
+    // ballot packing stages 1 KiB per wave (16 waves per block at most)
+    __shared__ __attribute__((aligned(16))) uint8_t stage_all[BALLOT ? 16 * 1024 : 16];
+    uint8_t *stage = BALLOT ? stage_all + 1024 * (threadIdx.x >> 6) : nullptr;
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     if (!header) {
         const Ranges r = extract_ranges(s);
-        extract_walk<K, UNR, NT>(s, r, 0, r.count, wave, n_waves, lane);
+        extract_walk<K, UNR, NT, BALLOT>(s, r, 0, r.count, wave, n_waves, lane, stage);
         return;
     }
     // Header mode.  Lane j < 32 reads the stego byte holding stream bit j;
@@ -80,10 +83,13 @@ __global__ void __launch_bounds__(1024)
     const Ranges r = extract_ranges(s);
     uint64_t v_begin = 0;
     if (pre && u_first >= r.fast_begin && u_first + G <= r.fast_end && u_first + G <= r.count) {
-        extract_store_group<K, UNR>(s, extract_out_base(s), u_first, c, lane);
+        if constexpr (BALLOT && K == 1)
+            extract_store_group_ballot<UNR>(s, extract_out_base(s), u_first, c, lane, stage);
+        else
+            extract_store_group<K, UNR>(s, extract_out_base(s), u_first, c, lane);
         v_begin = n_waves * G;  // the walk resumes at this wave's second group
     }
-    extract_walk<K, UNR, NT>(s, r, v_begin, r.count, wave, n_waves, lane);
+    extract_walk<K, UNR, NT, BALLOT>(s, r, v_begin, r.count, wave, n_waves, lane, stage);
 }
 
 // Per-byte embed for buffers whose cover or stego pointer is not 16-byte
@@ -136,10 +142,16 @@ struct Table {
         {lsb_embed_kernel<K, 2, false>, lsb_embed_kernel<K, 2, true>},
         {lsb_embed_kernel<K, 4, false>, lsb_embed_kernel<K, 4, true>}};
     static constexpr ExtractFn extract[3][2] = {
-        {lsb_extract_kernel<K, 1, false>, lsb_extract_kernel<K, 1, true>},
-        {lsb_extract_kernel<K, 2, false>, lsb_extract_kernel<K, 2, true>},
-        {lsb_extract_kernel<K, 4, false>, lsb_extract_kernel<K, 4, true>}};
+        {lsb_extract_kernel<K, 1, false, false>, lsb_extract_kernel<K, 1, true, false>},
+        {lsb_extract_kernel<K, 2, false, false>, lsb_extract_kernel<K, 2, true, false>},
+        {lsb_extract_kernel<K, 4, false, false>, lsb_extract_kernel<K, 4, true, false>}};
 };
+
+// k = 1 extract with wavefront-ballot packing.
+static constexpr ExtractFn extract_ballot_k1[3][2] = {
+    {lsb_extract_kernel<1, 1, false, true>, lsb_extract_kernel<1, 1, true, true>},
+    {lsb_extract_kernel<1, 2, false, true>, lsb_extract_kernel<1, 2, true, true>},
+    {lsb_extract_kernel<1, 4, false, true>, lsb_extract_kernel<1, 4, true, true>}};
 
 static EmbedFn embed_fn(int k, int u, int nt) {
     const int ui = unroll_index(u);
@@ -155,8 +167,9 @@ static EmbedFn embed_fn(int k, int u, int nt) {
     }
 }
 
-static ExtractFn extract_fn(int k, int u, int nt) {
+static ExtractFn extract_fn(int k, int u, int nt, int pack) {
     const int ui = unroll_index(u);
+    if (k == 1 && pack == 1) return extract_ballot_k1[ui][nt];
     switch (k) {
         case 1: return Table<1>::extract[ui][nt];
         case 2: return Table<2>::extract[ui][nt];
@@ -222,7 +235,7 @@ int launch_extract(const Span &s0, int header, uint64_t out_cap, uint32_t *len_o
         hipExtLaunchKernelGGL(lsb_extract_bytes_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, e0, e1, 0, s,
                               header, out_cap, len_out, status_out);
     } else {
-        ExtractFn fn = extract_fn(s.k, c.unroll, c.nontemporal);
+        ExtractFn fn = extract_fn(s.k, c.unroll, c.nontemporal, c.pack);
         hipEvent_t e0, e1;
         take_launch_events(&e0, &e1);
         hipExtLaunchKernelGGL(fn, dim3(grid_for(c, max_vectors)), dim3(c.block), 0, stream, e0, e1, 0, s, header,

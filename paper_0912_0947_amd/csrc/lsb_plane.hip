@@ -65,6 +65,46 @@ __global__ void __launch_bounds__(256) lsb_sse_kernel(const uint8_t *a, const ui
     if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
 }
 
+typedef void (*PlaneEmbedFn)(Span, uint32_t);
+typedef void (*PlaneExtractFn)(Span, uint32_t, uint64_t, uint32_t *, int32_t *);
+
+template <int K>
+struct PlaneTable {
+    static constexpr PlaneEmbedFn embed[3] = {lsb_plane_embed_vec_kernel<K, 2>, lsb_plane_embed_vec_kernel<K, 3>,
+                                              lsb_plane_embed_vec_kernel<K, 4>};
+    static constexpr PlaneExtractFn extract[3] = {lsb_plane_extract_vec_kernel<K, 2>,
+                                                  lsb_plane_extract_vec_kernel<K, 3>,
+                                                  lsb_plane_extract_vec_kernel<K, 4>};
+};
+
+static PlaneEmbedFn plane_embed_fn(int k, uint32_t c) {
+    const int ci = (int)c - 2;
+    switch (k) {
+        case 1: return PlaneTable<1>::embed[ci];
+        case 2: return PlaneTable<2>::embed[ci];
+        case 3: return PlaneTable<3>::embed[ci];
+        case 4: return PlaneTable<4>::embed[ci];
+        case 5: return PlaneTable<5>::embed[ci];
+        case 6: return PlaneTable<6>::embed[ci];
+        case 7: return PlaneTable<7>::embed[ci];
+        default: return PlaneTable<8>::embed[ci];
+    }
+}
+
+static PlaneExtractFn plane_extract_fn(int k, uint32_t c) {
+    const int ci = (int)c - 2;
+    switch (k) {
+        case 1: return PlaneTable<1>::extract[ci];
+        case 2: return PlaneTable<2>::extract[ci];
+        case 3: return PlaneTable<3>::extract[ci];
+        case 4: return PlaneTable<4>::extract[ci];
+        case 5: return PlaneTable<5>::extract[ci];
+        case 6: return PlaneTable<6>::extract[ci];
+        case 7: return PlaneTable<7>::extract[ci];
+        default: return PlaneTable<8>::extract[ci];
+    }
+}
+
 static unsigned grid_cap(uint64_t items) {
     uint64_t blocks = ceil_div(items ? items : 1, 256);
     const uint64_t cap = (uint64_t)device_cus() * 16;
@@ -94,8 +134,32 @@ int lsb_embed_plane(const uint8_t *cover, uint8_t *stego, uint64_t pixels, uint3
         return fail(LSB_E_ARG, "lsb_embed_plane: cover and stego overlap (only stego == cover is allowed)");
     if (overlaps(msg, len, stego, n)) return fail(LSB_E_ARG, "lsb_embed_plane: msg overlaps stego");
     hipStream_t st = (hipStream_t)stream;
+    const bool aligned = (((uintptr_t)cover | (uintptr_t)stego) & 15u) == 0;
+    if (c == 1) return lsb_embed(cover, stego, pixels, msg, len, k, stream);  // the plane is the image
+    if (aligned && c <= 4) {
+        // one pass: each lane moves 16 pixels (c vectors) and rewrites their plane bytes
+        Span s{};
+        s.src = cover;
+        s.dst = stego;
+        s.body = msg;
+        s.n = pixels;
+        s.bits = 8 * (4 + (uint64_t)len);
+        s.hdr = len;
+        s.hdr_len = 4;
+        s.k = k;
+        s.inplace = cover == stego;
+        s.words = (((uintptr_t)msg - 4) & 3u) == 0;
+        const Ranges r = embed_ranges(s);
+        if (!r.count) return LSB_OK;
+        hipEvent_t e0, e1;
+        take_launch_events(&e0, &e1);
+        hipExtLaunchKernelGGL(plane_embed_fn(k, c), dim3(grid_cap(r.count)), dim3(256), 0, st, e0, e1, 0, s, plane);
+        const hipError_t e = hipGetLastError();
+        return e == hipSuccess ? LSB_OK : hip_fail(e, "plane embed kernel launch");
+    }
+    // other channel counts or misaligned buffers: copy, then rewrite the plane bytes
     if (cover != stego) {
-        const int vec = (((uintptr_t)cover | (uintptr_t)stego) & 15u) == 0;
+        const int vec = aligned;
         hipLaunchKernelGGL(lsb_copy_kernel, dim3(grid_cap(vec ? n / 16 : n)), dim3(256), 0, st, cover, stego, n, vec);
     }
     Span s{};
@@ -130,6 +194,7 @@ int lsb_extract_plane(const uint8_t *stego, uint64_t pixels, uint32_t c, uint32_
     const uint64_t cap = room >= 4 ? room - 4 : 0;
     const uint64_t max_len = out_cap < cap ? out_cap : cap;
     if (overlaps(msg_out, max_len, stego, n)) return fail(LSB_E_ARG, "lsb_extract_plane: msg_out overlaps stego");
+    if (c == 1) return lsb_extract(stego, pixels, k, msg_out, out_cap, len_out_dev, status_out_dev, stream);
     Span s{};
     s.src = stego;
     s.out = msg_out;
@@ -138,8 +203,20 @@ int lsb_extract_plane(const uint8_t *stego, uint64_t pixels, uint32_t c, uint32_
     s.k = k;
     hipEvent_t e0, e1;
     take_launch_events(&e0, &e1);
-    hipExtLaunchKernelGGL(lsb_plane_extract_kernel, dim3(grid_cap(max_len)), dim3(256), 0, (hipStream_t)stream, e0, e1,
-                          0, s, c, plane, out_cap, len_out_dev, status_out_dev);
+    if (c <= 4 && ((uintptr_t)stego & 15u) == 0) {
+        s.words = (((uintptr_t)msg_out - 4) & 3u) == 0;
+        uint64_t vectors = 0;  // bound on the vectors a decodable stream can need
+        if ((uint64_t)k * pixels >= 32) {
+            const uint64_t v_stream = ceil_div(4 + max_len, 2 * (uint64_t)k);
+            const uint64_t v_buf = ceil_div(pixels, 16);
+            vectors = v_stream < v_buf ? v_stream : v_buf;
+        }
+        hipExtLaunchKernelGGL(plane_extract_fn(k, c), dim3(grid_cap(vectors)), dim3(256), 0, (hipStream_t)stream, e0,
+                              e1, 0, s, plane, out_cap, len_out_dev, status_out_dev);
+    } else {
+        hipExtLaunchKernelGGL(lsb_plane_extract_kernel, dim3(grid_cap(max_len)), dim3(256), 0, (hipStream_t)stream,
+                              e0, e1, 0, s, c, plane, out_cap, len_out_dev, status_out_dev);
+    }
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? LSB_OK : hip_fail(e, "plane extract kernel launch");
 }

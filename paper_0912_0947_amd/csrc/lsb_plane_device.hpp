@@ -95,4 +95,151 @@ __global__ void __launch_bounds__(256) lsb_plane_extract_kernel(Span s, uint32_t
         s.out[m] = (uint8_t)plane_stream_byte(s, m + 4, c, plane);
 }
 
+// ---------------------------------------------------------------------------
+// Vector form for C in {2, 3, 4} channels: a lane moves 16 pixels = C
+// 16-byte vectors, gathers their plane bytes into one 16-field vector, runs
+// the plain vector embed / extract on it and scatters the result back.  All
+// byte positions are compile-time constants (C and PLANE are template
+// parameters), so the gather and scatter are register bit-field moves.
+template <int C, int PLANE>
+__device__ __forceinline__ u32x4 plane_gather(const u32x4 *v) {
+    u32x4 p = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int f = 0; f < 16; ++f) {
+        const int b = f * C + PLANE;
+        const uint32_t byte = (v[b >> 4][(b & 15) >> 2] >> (8 * (b & 3))) & 0xFFu;
+        p[f >> 2] |= byte << (8 * (f & 3));
+    }
+    return p;
+}
+
+template <int C, int PLANE>
+__device__ __forceinline__ void plane_scatter(u32x4 *v, u32x4 p) {
+#pragma unroll
+    for (int f = 0; f < 16; ++f) {
+        const int b = f * C + PLANE;
+        const uint32_t byte = (p[f >> 2] >> (8 * (f & 3))) & 0xFFu;
+        const int sh = 8 * (b & 3);
+        v[b >> 4][(b & 15) >> 2] = (v[b >> 4][(b & 15) >> 2] & ~(0xFFu << sh)) | (byte << sh);
+    }
+}
+
+template <int K, int C, int PLANE>
+__device__ __forceinline__ void plane_embed_vec(u32x4 *v, const uint32_t *w) {
+    plane_scatter<C, PLANE>(v, embed_vec<K>(plane_gather<C, PLANE>(v), w));
+}
+
+template <int K, int C>
+__device__ __forceinline__ void plane_embed_vec_any(u32x4 *v, const uint32_t *w, uint32_t plane) {
+    switch (plane) {  // uniform across the grid
+        case 0: plane_embed_vec<K, C, 0>(v, w); break;
+        case 1: plane_embed_vec<K, C, 1>(v, w); break;
+        case 2: if constexpr (C > 2) plane_embed_vec<K, C, 2>(v, w); break;
+        default: if constexpr (C > 3) plane_embed_vec<K, C, 3>(v, w); break;
+    }
+}
+
+template <int K, int C>
+__device__ __forceinline__ u32x4 plane_gather_any(const u32x4 *v, uint32_t plane) {
+    switch (plane) {
+        case 0: return plane_gather<C, 0>(v);
+        case 1: return plane_gather<C, 1>(v);
+        case 2: if constexpr (C > 2) return plane_gather<C, 2>(v); break;
+        default: if constexpr (C > 3) return plane_gather<C, 3>(v); break;
+    }
+    return u32x4{0u, 0u, 0u, 0u};
+}
+
+// Embed over the plane view; s.n = pixels, s.src/s.dst the interleaved
+// cover/stego (16-byte aligned), header mode (t0 = 0).  Edge vectors (header
+// bytes, partial field, pixel tail) go field by field.
+template <int K, int C>
+__global__ void __launch_bounds__(256) lsb_plane_embed_vec_kernel(Span s, uint32_t plane) {
+    const Ranges r = embed_ranges(s);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uintptr_t body_base = (uintptr_t)s.body - s.hdr_len;  // stream byte i at body_base + i
+    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < r.count; u += stride) {
+        uint8_t *dst = s.dst + 16 * C * u;
+        const uint8_t *src = s.src + 16 * C * u;
+        if (u >= r.fast_begin && u < r.fast_end) {
+            u32x4 v[C];
+#pragma unroll
+            for (int i = 0; i < C; ++i) v[i] = load16<true>(src + 16 * i);
+            uint32_t w[Chunk<K>::NW];
+            const uint8_t *p = reinterpret_cast<const uint8_t *>(body_base + 2 * K * u);
+            if (s.words) load_chunk_words<K>(p, w);
+            else load_chunk_bytes<K>(p, 0, w);
+            plane_embed_vec_any<K, C>(v, w, plane);
+#pragma unroll
+            for (int i = 0; i < C; ++i) store16<true>(dst + 16 * i, v[i]);
+        } else if (u >= r.copy_begin && u < r.copy_end) {
+            if (!s.inplace) {
+#pragma unroll
+                for (int i = 0; i < C; ++i) store16<true>(dst + 16 * i, load16<true>(src + 16 * i));
+            }
+        } else {
+            const uint64_t px_end = 16 * u + 16 < s.n ? 16 * u + 16 : s.n;
+            for (uint64_t px = 16 * u; px < px_end; ++px) {
+                if (!s.inplace)
+                    for (uint32_t ch = 0; ch < (uint32_t)C; ++ch)
+                        if (ch != plane) s.dst[px * C + ch] = s.src[px * C + ch];
+                const uint64_t at = plane_byte(px, C, plane);
+                if ((uint64_t)s.k * px >= s.bits) {
+                    if (!s.inplace) s.dst[at] = s.src[at];
+                } else {
+                    plane_embed_field(s, px, C, plane);
+                }
+            }
+        }
+    }
+}
+
+// Extract over the plane view: header decode per wave (lane j < 32 reads
+// stream bit j), status through block 0, then 2K message bytes per lane.
+template <int K, int C>
+__global__ void __launch_bounds__(256)
+    lsb_plane_extract_vec_kernel(Span s, uint32_t plane, uint64_t out_cap, uint32_t *len_out, int32_t *status_out) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t len = 0;
+    int status = LSB_E_HEADER;
+    if ((uint64_t)K * s.n >= 32) {
+        uint32_t bit = 0;
+        if (lane < 32) bit = (s.src[plane_byte(lane / K, C, plane)] >> (K - 1 - lane % K)) & 1u;
+        len = __builtin_bitreverse32((uint32_t)__ballot(bit));
+        if (4 + (uint64_t)len > room_bytes(s.n, K)) status = LSB_E_HEADER;
+        else if ((uint64_t)len > out_cap) status = LSB_E_BUFFER;
+        else status = LSB_OK;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *len_out = len;
+        *status_out = status;
+    }
+    if (status != LSB_OK) return;
+    s.bits = 8 * (4 + (uint64_t)len);
+    const Ranges r = extract_ranges(s);
+    const uintptr_t out_base = (uintptr_t)s.out - s.hdr_len;
+    const uint64_t end_byte = ceil_div(s.bits, 8);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < r.count; u += stride) {
+        if (u >= r.fast_begin && u < r.fast_end) {
+            u32x4 v[C];
+#pragma unroll
+            for (int i = 0; i < C; ++i) v[i] = load16<true>(s.src + 16 * (C * u + i));
+            uint32_t w[Chunk<K>::NW];
+            extract_vec<K>(plane_gather_any<K, C>(v, plane), w);
+            uint8_t *p = reinterpret_cast<uint8_t *>(out_base + 2 * K * u);
+            if (s.words) {
+                store_chunk_words<K>(p, w);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 2 * K; ++i) p[i] = (uint8_t)(w[i >> 2] >> (24 - 8 * (i & 3)));
+            }
+        } else {
+            const uint64_t i0 = 2 * K * u;
+            for (uint64_t i = i0; i < i0 + 2 * K && i < end_byte; ++i)
+                if (i >= s.hdr_len) s.out[i - s.hdr_len] = (uint8_t)plane_stream_byte(s, i, C, plane);
+        }
+    }
+}
+
 }  // namespace lsb

@@ -56,6 +56,8 @@ extern "C" int lsb_autotune(int op, int k, uint64_t n, uint8_t *cover, uint8_t *
     hipEvent_t ev0, ev1;
     hipEventCreate(&ev0);
     hipEventCreate(&ev1);
+    hipEventRecord(ev0, stream);  // both events exist in a recorded state before the first timing
+    hipEventRecord(ev1, stream);
 
     // For extract, the stego buffer must carry a full-capacity stream.
     Span base{};
@@ -77,17 +79,19 @@ extern "C" int lsb_autotune(int op, int k, uint64_t n, uint8_t *cover, uint8_t *
     const int caps[] = {0, 2, 4, 8, 16};
     double best_t = 1e30;
     lsb_launch_cfg best_c = tune_lookup(op, k, n);
+    const int packs = (op == LSB_OP_EXTRACT && k == 1) ? 2 : 1;  // ballot packing exists for k = 1
+    for (int pk = 0; pk < packs && rc == LSB_OK; ++pk)
     for (int nt = 0; nt < 2 && rc == LSB_OK; ++nt)
         for (int b : blocks)
             for (int u : unrolls)
                 for (int c : caps) {
                     if (rc != LSB_OK) break;
-                    const lsb_launch_cfg cfg{b, u, c, nt};
+                    const lsb_launch_cfg cfg{b, u, c, nt, pk};
                     double total = 0;
                     for (int r = 0; r < reps && rc == LSB_OK; ++r) {
                         rc = flush.run(stream);
                         if (rc) break;
-                        hipEventRecord(ev0, stream);
+                        set_launch_events(ev0, ev1);  // bound to the kernel's own begin and end
                         if (op == LSB_OP_EMBED) {
                             Span s = base;
                             s.src = cover;
@@ -105,7 +109,6 @@ extern "C" int lsb_autotune(int op, int k, uint64_t n, uint8_t *cover, uint8_t *
                             rc = launch_extract(s, 1, (uint64_t)cap, status, (int32_t *)(status + 1),
                                                 v_stream < v_buf ? v_stream : v_buf, cfg, stream);
                         }
-                        hipEventRecord(ev1, stream);
                         e = hipEventSynchronize(ev1);
                         if (e != hipSuccess) {
                             rc = hip_fail(e, "hipEventSynchronize(autotune)");

@@ -48,12 +48,12 @@ def load(handle=None, path: str = TABLE) -> bool:
         keys = sorted(tuned)
         for b in range(64):
             c = tuned[min(keys, key=lambda t: (abs(t - b), t))]
-            cfg = LaunchCfg(c["block"], c["unroll"], c["blocks_per_cu"], c["nontemporal"])
+            cfg = LaunchCfg(c["block"], c["unroll"], c["blocks_per_cu"], c["nontemporal"], c.get("pack", 0))
             if handle.lsb_tune_set(op, k, b, ctypes.byref(cfg)) != 0:
                 raise RuntimeError("bad tuning entry %s" % c)
     if "batch" in table:
         c = table["batch"]["cfg"]
-        cfg = LaunchCfg(c["block"], c["unroll"], c["blocks_per_cu"], c["nontemporal"])
+        cfg = LaunchCfg(c["block"], c["unroll"], c["blocks_per_cu"], c["nontemporal"], 0)
         if handle.lsb_batch_tune_set(ctypes.byref(cfg), int(table["batch"]["tile_vectors"])) != 0:
             raise RuntimeError("bad batch tuning entry %s" % table["batch"])
     _ = check

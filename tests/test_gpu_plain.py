@@ -318,3 +318,25 @@ def test_cover_beyond_4gib(k):
     ls = ls.cpu().numpy()
     assert ls[1] == OK and int(np.uint32(ls[0])) == ln
     assert torch.equal(out[:ln], msg)
+
+
+@pytest.mark.parametrize("block,unroll,nt", [(256, 1, 0), (512, 2, 1), (1024, 4, 1), (256, 4, 0)])
+def test_ballot_packing_parity(block, unroll, nt):
+    """k = 1 extraction with wavefront-ballot packing (LDS-staged) gives the
+    oracle's message on aligned, ragged and misaligned outputs."""
+    from paper_0912_0947_amd import tune
+    try:
+        api.tune_set(api.OP_EXTRACT, 1, -1, block, unroll, 0, nt, pack=1)
+        for n, off in [(786432, 0), (1000003, 0), (65536 * 3 + 17, 4), (100000, 1), (33, 0)]:
+            cover = inputs.random_bytes(n, 1951, n)
+            cap = oracle.capacity(n, 1)
+            for ln in sorted({cap, cap // 3, 0}):
+                msg = inputs.random_bytes(ln, 1952, n, ln)
+                rc, st = oracle.embed(cover, msg, 1)
+                out = empty_dev(max(cap, 1), pad_before=off)
+                out, ls = api.extract(to_dev(st), 1, out=out[:cap] if cap else out[:0])
+                ls = ls.cpu().numpy()
+                assert ls[1] == OK and ls[0] == ln
+                assert_bytes_equal(to_host(out)[:ln], msg, "ballot n=%d len=%d off=%d" % (n, ln, off))
+    finally:
+        tune.load()
