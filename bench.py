@@ -196,7 +196,7 @@ def bench_paper_layout(api, lib_handle, cover, dev, reps=5):
     return res
 
 
-def bench_quality(api, lib_handle, cover, stego_by_k, dev, reps=5):
+def bench_quality(api, lib_handle, cover, stego_by_k, msgs_by_k, dev, reps=5):
     """Section VIII's quality figure on the large image: PSNR of each stego
     against its cover over all bytes, from the device squared-error kernel
     (algorithmic bytes 2n per launch), and single-plane embedding at the
@@ -224,6 +224,24 @@ def bench_quality(api, lib_handle, cover, stego_by_k, dev, reps=5):
             ms.append(e0.elapsed_time(e1))
     us = sorted(ms)[len(ms) // 2] * 1e3
     out["sse_kernel"] = {"bytes": 2 * n, "us_median": round(us, 2), "GBps": round(2 * n / (us * 1e-6) / 1e9, 1)}
+    # one-launch verification of the k = 1 stego (reads cover, stego, stream)
+    cnt = torch.empty(1, dtype=torch.int64, device=dev)
+    ms = []
+    for r in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        e1.record()
+        torch.cuda.synchronize()
+        lib_handle.lsb_time_next_launch(e0, e1)
+        api.verify(cover, stego_by_k[1], msgs_by_k[1], 1, out=cnt)
+        torch.cuda.synchronize()
+        if r:
+            ms.append(e0.elapsed_time(e1))
+    assert int(cnt.item()) == 0, "verification found mismatches"
+    us = sorted(ms)[len(ms) // 2] * 1e3
+    b = 2 * n + 4 + msgs_by_k[1].numel()
+    out["verify_k1"] = {"bytes": b, "us_median": round(us, 2), "GBps": round(b / (us * 1e-6) / 1e9, 1),
+                        "mismatches": 0}
     pixels = n // 3
     msg = torch.empty(api.capacity(pixels, 2), dtype=torch.uint8, device=dev)
     inputs.fill_uniform(msg, 1701)
@@ -489,7 +507,7 @@ def main():
         "copy_reference": copy_ref,
     }
     result["paper_layout"] = bench_paper_layout(api, L, covers[0], dev)
-    result["quality"] = bench_quality(api, L, covers[0], {k: stegos[k][1] for k in KS}, dev)
+    result["quality"] = bench_quality(api, L, covers[0], {k: stegos[k][1] for k in KS}, msgs, dev)
 
     if not args.no_batched:
         from paper_0912_0947_amd import batch, serve

@@ -174,6 +174,16 @@ int lsb_video_embed_host(const uint8_t *host_frames, uint8_t *host_stego,
                          void *s_in, void *s_compute, void *s_out);
 
 /* ------------------------------------------------------------------------
+ * Verification in one launch: *mismatches_dev (overwritten) receives the
+ * number of bytes t < n where stego[t] differs from what lsb_embed(cover,
+ * msg, len, k) writes (Section VI step 7 recomputed from cover and message).
+ * Zero means stego carries exactly msg, so extraction (Section VII step 6)
+ * returns it.  Reads cover, stego and the stream once; writes one counter. */
+int lsb_verify(const uint8_t *cover, const uint8_t *stego, uint64_t n,
+               const uint8_t *msg, uint32_t len, int k,
+               uint64_t *mismatches_dev, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched form: thousands of covers of uneven size and k in one persistent
  * launch (the paper's per-row loop over an image, Section VI steps 4-5, and
  * its frame loop over a video, generalised to independent covers).

@@ -14,7 +14,7 @@ from ._lib import (E_ARG, OK, OP_EMBED, OP_EXTRACT, LaunchCfg, LsbError, check, 
 
 __all__ = ["capacity", "embed", "extract", "extract_sync", "embed_raw", "extract_raw",
            "paper_capacity", "paper_embed", "paper_extract", "embed_plane", "extract_plane", "sse", "psnr",
-           "video_embed_host",
+           "video_embed_host", "verify",
            "tune_get", "tune_set", "autotune", "LsbError", "OK", "OP_EMBED", "OP_EXTRACT"]
 
 
@@ -196,6 +196,19 @@ def video_embed_host(host_frames: torch.Tensor, host_stego: torch.Tensor, frame_
                                      frame_bytes, host_frames.numel() // frame_bytes, _u8(stream_bytes, "stream_bytes"),
                                      stream_bits, k, _u8(ring, "ring"), slots, ctypes.c_void_p(s_in.cuda_stream),
                                      ctypes.c_void_p(s_c.cuda_stream), ctypes.c_void_p(s_out.cuda_stream)))
+
+
+def verify(cover: torch.Tensor, stego: torch.Tensor, msg: torch.Tensor, k: int,
+           out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Count (on the device, int64 tensor of 1 element) the stego bytes that
+    differ from the embedding of ``msg`` into ``cover``; 0 means verified."""
+    if cover.numel() != stego.numel():
+        raise ValueError("cover and stego must have the same size")
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=cover.device)
+    check(lib().lsb_verify(_u8(cover, "cover"), _u8(stego, "stego"), cover.numel(), _u8(msg, "msg"), msg.numel(), k,
+                           ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
 
 
 def tune_get(op: int, k: int, n: int) -> dict:
