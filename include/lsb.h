@@ -337,6 +337,16 @@ int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *requests, int n_requ
  * packets.  Applies to one launch, then clears.  Both may be NULL to clear. */
 int lsb_time_next_launch(void *start_event, void *stop_event);
 
+/* The same scheduler without a GPU: launches are modelled (a launch of
+ * jobs moving B algorithmic bytes finishes launch_us + B / device_gbps after
+ * it starts, every job succeeds, nothing is computed) on a virtual clock
+ * that jumps to the next arrival or completion when idle.  cfg's buffers are
+ * not touched (they may be NULL); arena_bytes is the budget.  For testing
+ * admission, batching and eviction on the host. */
+int lsb_serve_simulate(const lsb_server_cfg *cfg, const lsb_request *requests, int n_requests,
+                       lsb_result *results, lsb_serve_stats *stats, double launch_us,
+                       double device_gbps);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char *lsb_last_error(void);
 

@@ -103,6 +103,8 @@ SIGNATURES = {
     "lsb_batch_tune_get": (_I, [ctypes.POINTER(LaunchCfg), ctypes.POINTER(_I64)]),
     "lsb_batch_tune_set": (_I, [ctypes.POINTER(LaunchCfg), _I64]),
     "lsb_serve": (_I, [ctypes.POINTER(ServerCfg), _P, _I, _P, ctypes.POINTER(ServeStats)]),
+    "lsb_serve_simulate": (_I, [ctypes.POINTER(ServerCfg), _P, _I, _P, ctypes.POINTER(ServeStats),
+                                ctypes.c_double, ctypes.c_double]),
     "lsb_time_next_launch": (_I, [_P, _P]),
     "lsb_last_error": (ctypes.c_char_p, []),
     "lsb_version": (ctypes.c_char_p, []),

@@ -10,6 +10,12 @@
 // events; stego buffers stay resident until an extract consumes them or the
 // budget needs their space (oldest first).
 //
+// The scheduler is written against an executor interface.  lsb_serve runs it
+// with the HIP executor on the real clock; lsb_serve_simulate runs the same
+// scheduler with a host-only executor whose launches finish after a modelled
+// time on a virtual clock, so that admission, batching and eviction can be
+// tested without a GPU.
+//
 // The paper serves one image row per blocking MEX call (Section V: copy in,
 // launch, copy out); the roles of that call -- validate, place on the
 // device, run, return -- are kept, spread over many requests in flight.
@@ -35,7 +41,7 @@ inline uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign
 // First-fit allocator over [0, size) in 256-byte granules.
 class Arena {
    public:
-    explicit Arena(uint64_t size) : size_(size) {
+    explicit Arena(uint64_t size) {
         if (size) free_[0] = size;
     }
     bool alloc(uint64_t bytes, uint64_t *off) {
@@ -73,43 +79,180 @@ class Arena {
     uint64_t peak() const { return peak_; }
 
    private:
-    uint64_t size_;
     uint64_t used_ = 0, peak_ = 0;
     std::map<uint64_t, uint64_t> free_;
 };
 
-struct Slot {
-    lsb_plan *plan[2] = {nullptr, nullptr};  // [op]
-    hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
-    uint64_t status_off = 0;  // arena offset of 2 x max_batch int32 statuses
-    uint64_t len_off = 0;     // arena offset of 2 x max_batch uint32 lengths
-    int32_t *status_host = nullptr;
-    uint32_t *len_host = nullptr;
-    std::vector<int> reqs[2];
-    bool busy = false;
-};
-
-struct Served {
-    uint64_t out_bytes = 0;  // bytes of the output allocation
-    bool live = false;       // embed: stego resident and not yet claimed
-};
-
 double embed_bytes(uint64_t n, uint32_t len) { return 2.0 * (double)n + 4.0 + (double)len; }
-double extract_bytes(uint64_t n_unused, uint32_t len, int k) {
-    (void)n_unused;
+double extract_bytes(uint32_t len, int k) {
     return (double)ceil_div(8 * (4 + (uint64_t)len), (uint64_t)k) + (double)len;
 }
 
-}  // namespace
+// ---------------------------------------------------------------------------
+// Executors.  launch() takes a slot's embed and extract job lists (either may
+// be empty); poll() reports whether the slot's launch has finished and then
+// fills the per-job status and decoded length.
+struct Executor {
+    virtual ~Executor() {}
+    virtual int launch(int slot, const lsb_job *jobs_e, int ne, const lsb_job *jobs_x, int nx) = 0;
+    virtual int poll(int slot, bool *done) = 0;
+    virtual int32_t status(int slot, int op, int j) const = 0;
+    virtual uint32_t length(int slot, int op, int j) const = 0;
+    virtual double now() = 0;
+    // Nothing can happen before `t` (next arrival) unless a launch finishes:
+    // a virtual clock jumps there; the real clock just keeps running.
+    virtual void idle(double t) = 0;
+};
 
-extern "C" int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *req, int n_req, lsb_result *res,
-                         lsb_serve_stats *stats) {
-    clear_error();
-    if (!cfg || (!req && n_req) || (!res && n_req) || n_req < 0)
-        return fail(LSB_E_ARG, "lsb_serve: null argument");
-    if (!cfg->arena || ((uintptr_t)cfg->arena & 255) || ((uintptr_t)cfg->cover_pool & 255) ||
-        ((uintptr_t)cfg->msg_pool & 255))
+class HipExecutor : public Executor {
+   public:
+    HipExecutor(const lsb_server_cfg *cfg, int slots, int batch) : cfg_(cfg), B_(batch), s_(slots) {
+        t0_ = std::chrono::steady_clock::now();
+    }
+    ~HipExecutor() override {
+        for (S &s : s_) {
+            if (s.busy && s.done) hipEventSynchronize(s.done);
+            for (lsb_plan *p : s.plan)
+                if (p) lsb_plan_destroy(p);
+            if (s.done) hipEventDestroy(s.done);
+            if (s.stream) hipStreamDestroy(s.stream);
+            if (s.status_host) hipHostFree(s.status_host);
+            if (s.len_host) hipHostFree(s.len_host);
+        }
+    }
+    // status_off / len_off: arena offsets of 2*B int32 / uint32 per slot
+    int init(const std::vector<uint64_t> &status_off, const std::vector<uint64_t> &len_off) {
+        for (size_t i = 0; i < s_.size(); ++i) {
+            S &s = s_[i];
+            s.status_dev = (int32_t *)(cfg_->arena + status_off[i]);
+            s.len_dev = (uint32_t *)(cfg_->arena + len_off[i]);
+            hipError_t e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipHostMalloc((void **)&s.status_host, sizeof(int32_t) * 2 * B_, hipHostMallocDefault);
+            if (e == hipSuccess) e = hipHostMalloc((void **)&s.len_host, sizeof(uint32_t) * 2 * B_, hipHostMallocDefault);
+            if (e != hipSuccess) return hip_fail(e, "lsb_serve: slot setup");
+            for (int op = 0; op < 2; ++op) {
+                const int rc = lsb_plan_create(&s.plan[op], B_);
+                if (rc != LSB_OK) return rc;
+            }
+        }
+        return LSB_OK;
+    }
+    int launch(int slot, const lsb_job *jobs_e, int ne, const lsb_job *jobs_x, int nx) override {
+        S &s = s_[slot];
+        const lsb_job *jobs[2] = {jobs_e, jobs_x};
+        const int cnt[2] = {ne, nx};
+        for (int op = 0; op < 2; ++op) {
+            if (!cnt[op]) continue;
+            int rc = lsb_plan_set_jobs(s.plan[op], jobs[op], cnt[op]);
+            if (rc != LSB_OK) return rc;
+            int32_t *st = s.status_dev + op * B_;
+            uint32_t *ln = s.len_dev + op * B_;
+            rc = lsb_plan_run(s.plan[op], op == LSB_OP_EMBED ? cfg_->cover_pool : nullptr, cfg_->arena,
+                              op == LSB_OP_EMBED ? (uint8_t *)cfg_->msg_pool : cfg_->arena, ln, st, s.stream);
+            if (rc != LSB_OK) return rc;
+            hipError_t e = hipMemcpyAsync(s.status_host + op * B_, st, sizeof(int32_t) * cnt[op],
+                                          hipMemcpyDeviceToHost, s.stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(s.len_host + op * B_, ln, sizeof(uint32_t) * cnt[op], hipMemcpyDeviceToHost,
+                                   s.stream);
+            if (e != hipSuccess) return hip_fail(e, "lsb_serve: status copy");
+        }
+        const hipError_t e = hipEventRecord(s.done, s.stream);
+        if (e != hipSuccess) return hip_fail(e, "lsb_serve: event record");
+        s.busy = true;
+        return LSB_OK;
+    }
+    int poll(int slot, bool *done) override {
+        S &s = s_[slot];
+        const hipError_t q = hipEventQuery(s.done);
+        if (q == hipErrorNotReady) {
+            *done = false;
+            return LSB_OK;
+        }
+        if (q != hipSuccess) return hip_fail(q, "lsb_serve: event query");
+        s.busy = false;
+        *done = true;
+        return LSB_OK;
+    }
+    int32_t status(int slot, int op, int j) const override { return s_[slot].status_host[op * B_ + j]; }
+    uint32_t length(int slot, int op, int j) const override { return s_[slot].len_host[op * B_ + j]; }
+    double now() override {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
+    }
+    void idle(double) override {}
+
+   private:
+    struct S {
+        lsb_plan *plan[2] = {nullptr, nullptr};
+        hipStream_t stream = nullptr;
+        hipEvent_t done = nullptr;
+        int32_t *status_dev = nullptr;
+        uint32_t *len_dev = nullptr;
+        int32_t *status_host = nullptr;
+        uint32_t *len_host = nullptr;
+        bool busy = false;
+    };
+    const lsb_server_cfg *cfg_;
+    int B_;
+    std::vector<S> s_;
+    std::chrono::steady_clock::time_point t0_;
+};
+
+// Host-only executor on a virtual clock: a launch finishes
+// fixed_us + bytes / gbps after it starts, slots run independently, every
+// job succeeds (extract jobs report their message capacity as the decoded
+// length).  Nothing is computed.
+class SimExecutor : public Executor {
+   public:
+    SimExecutor(int slots, int batch, double fixed_us, double gbps)
+        : B_(batch), fixed_(fixed_us * 1e-6), gbps_(gbps), s_(slots) {
+        for (S &s : s_) s.len.assign(2 * (size_t)batch, 0);
+    }
+    int launch(int slot, const lsb_job *jobs_e, int ne, const lsb_job *jobs_x, int nx) override {
+        S &s = s_[slot];
+        double bytes = 0;
+        for (int j = 0; j < ne; ++j) bytes += embed_bytes(jobs_e[j].n, jobs_e[j].len);
+        for (int j = 0; j < nx; ++j) {
+            bytes += extract_bytes((uint32_t)jobs_x[j].msg_cap, jobs_x[j].k);
+            s.len[B_ + j] = (uint32_t)jobs_x[j].msg_cap;
+        }
+        for (int j = 0; j < ne; ++j) s.len[j] = jobs_e[j].len;
+        s.finish = t_ + fixed_ + bytes / (gbps_ * 1e9);
+        s.busy = true;
+        return LSB_OK;
+    }
+    int poll(int slot, bool *done) override {
+        S &s = s_[slot];
+        *done = s.busy && t_ >= s.finish;
+        if (*done) s.busy = false;
+        return LSB_OK;
+    }
+    int32_t status(int, int, int) const override { return LSB_OK; }
+    uint32_t length(int slot, int op, int j) const override { return s_[slot].len[op * B_ + j]; }
+    double now() override { return t_; }
+    void idle(double t) override {
+        double next = t;
+        for (const S &s : s_)
+            if (s.busy) next = std::min(next, s.finish);
+        if (next > t_ && next < 1e300) t_ = next;
+    }
+
+   private:
+    struct S {
+        double finish = 0;
+        bool busy = false;
+        std::vector<uint32_t> len;
+    };
+    int B_;
+    double fixed_, gbps_, t_ = 0;
+    std::vector<S> s_;
+};
+
+int check_args(const lsb_server_cfg *cfg, const lsb_request *req, int n_req, lsb_result *res, bool device) {
+    if (!cfg || (!req && n_req) || (!res && n_req) || n_req < 0) return fail(LSB_E_ARG, "lsb_serve: null argument");
+    if (device && (!cfg->arena || ((uintptr_t)cfg->arena & 255) || ((uintptr_t)cfg->cover_pool & 255) ||
+                   ((uintptr_t)cfg->msg_pool & 255)))
         return fail(LSB_E_ARG, "lsb_serve: arena and pools must be 256-byte aligned device buffers");
     if (cfg->max_batch < 1 || cfg->max_batch > 65536 || cfg->n_slots < 1 || cfg->n_slots > 16 || cfg->reserved)
         return fail(LSB_E_ARG, "lsb_serve: max_batch 1..65536, n_slots 1..16, reserved 0");
@@ -124,42 +267,18 @@ extern "C" int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *req, int 
         const uint64_t room = room_bytes(r.n, r.k);
         if (room < 4 || r.len > room - 4) return fail(LSB_E_CAPACITY, "request %d: message exceeds capacity", i);
     }
+    return LSB_OK;
+}
 
+struct Served {
+    uint64_t out_bytes = 0;  // bytes of the output allocation
+    bool live = false;       // embed: stego resident and not yet claimed
+};
+
+// The scheduler.  `arena` already holds the per-slot status arrays.
+int run_scheduler(const lsb_server_cfg *cfg, const lsb_request *req, int n_req, lsb_result *res,
+                  lsb_serve_stats *stats, Executor &ex, Arena &arena) {
     const int B = cfg->max_batch, S = cfg->n_slots;
-    Arena arena(cfg->arena_bytes);
-    std::vector<Slot> slots(S);
-    int rc = LSB_OK;
-    auto cleanup = [&]() {
-        for (Slot &s : slots) {
-            if (s.busy && s.done) hipEventSynchronize(s.done);
-            for (lsb_plan *p : s.plan)
-                if (p) lsb_plan_destroy(p);
-            if (s.done) hipEventDestroy(s.done);
-            if (s.stream) hipStreamDestroy(s.stream);
-            if (s.status_host) hipHostFree(s.status_host);
-            if (s.len_host) hipHostFree(s.len_host);
-        }
-    };
-    for (Slot &s : slots) {
-        if (!arena.alloc(sizeof(int32_t) * 2 * B, &s.status_off) || !arena.alloc(sizeof(uint32_t) * 2 * B, &s.len_off)) {
-            cleanup();
-            return fail(LSB_E_NOMEM, "lsb_serve: arena too small for per-slot status arrays");
-        }
-        hipError_t e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&s.status_host, sizeof(int32_t) * 2 * B, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&s.len_host, sizeof(uint32_t) * 2 * B, hipHostMallocDefault);
-        if (e != hipSuccess) {
-            cleanup();
-            return hip_fail(e, "lsb_serve: slot setup");
-        }
-        for (int op = 0; op < 2 && rc == LSB_OK; ++op) rc = lsb_plan_create(&s.plan[op], B);
-        if (rc != LSB_OK) {
-            cleanup();
-            return rc;
-        }
-    }
-
     std::vector<Served> sv(n_req);
     for (int i = 0; i < n_req; ++i) {
         lsb_result &r = res[i];
@@ -170,18 +289,19 @@ extern "C" int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *req, int 
         r.k = req[i].k;
     }
     std::deque<int> waiting, ready, live;  // arrived / admitted / completed embeds with resident stego
-    std::vector<lsb_job> jobs((size_t)B);
+    std::vector<std::vector<int>> slot_reqs[2];
+    for (int op = 0; op < 2; ++op) slot_reqs[op].resize(S);
+    std::vector<bool> busy(S, false);
+    std::vector<lsb_job> jobs[2] = {std::vector<lsb_job>((size_t)B), std::vector<lsb_job>((size_t)B)};
     std::vector<double> lat;
     lat.reserve(n_req);
-    int next = 0, finished = 0;
+    int next = 0, finished = 0, rc = LSB_OK;
     int64_t launches = 0, evictions = 0, stalls = 0, rejected = 0, batched = 0;
     bool stalled = false;
     double bytes = 0, first_arrival = n_req ? req[0].arrival_s : 0, last_done = 0;
-    const auto t0 = std::chrono::steady_clock::now();
-    auto now_s = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
     auto in_flight = [&]() {
-        for (const Slot &s : slots)
-            if (s.busy) return true;
+        for (int s = 0; s < S; ++s)
+            if (busy[s]) return true;
         return !ready.empty();
     };
     auto release_out = [&](int i) {
@@ -192,7 +312,8 @@ extern "C" int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *req, int 
     };
 
     while (finished < n_req && rc == LSB_OK) {
-        double now = now_s();
+        double now = ex.now();
+        bool progressed = false;
         while (next < n_req && req[next].arrival_s <= now) waiting.push_back(next++);
 
         // ---- admission, in arrival order, against the HBM budget
@@ -239,10 +360,12 @@ extern "C" int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *req, int 
                 ++rejected;
                 ++finished;
                 waiting.pop_front();
+                progressed = true;
                 continue;
             }
             stalled = false;
             waiting.pop_front();
+            progressed = true;
             r.admit_s = now;
             r.out_off = off;
             sv[i].out_bytes = need;
@@ -258,24 +381,21 @@ extern "C" int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *req, int 
         }
 
         // ---- launch admitted requests on free slots
-        for (Slot &s : slots) {
-            if (ready.empty() || rc != LSB_OK) break;
-            if (s.busy) continue;
-            s.reqs[0].clear();
-            s.reqs[1].clear();
+        for (int s = 0; s < S && !ready.empty() && rc == LSB_OK; ++s) {
+            if (busy[s]) continue;
+            slot_reqs[0][s].clear();
+            slot_reqs[1][s].clear();
             for (int c = 0; c < B && !ready.empty(); ++c) {
                 const int i = ready.front();
                 ready.pop_front();
-                s.reqs[res[i].op_run].push_back(i);
+                slot_reqs[res[i].op_run][s].push_back(i);
             }
-            now = now_s();
-            uint8_t *arena_p = cfg->arena;
-            for (int op = 0; op < 2 && rc == LSB_OK; ++op) {
-                const std::vector<int> &ids = s.reqs[op];
-                if (ids.empty()) continue;
+            now = ex.now();
+            for (int op = 0; op < 2; ++op) {
+                const std::vector<int> &ids = slot_reqs[op][s];
                 for (size_t j = 0; j < ids.size(); ++j) {
                     const int i = ids[j];
-                    lsb_job &J = jobs[j];
+                    lsb_job &J = jobs[op][j];
                     memset(&J, 0, sizeof J);
                     J.op = (uint8_t)op;
                     if (op == LSB_OP_EMBED) {
@@ -295,47 +415,31 @@ extern "C" int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *req, int 
                     }
                     res[i].launch_s = now;
                 }
-                rc = lsb_plan_set_jobs(s.plan[op], jobs.data(), (int)ids.size());
-                if (rc != LSB_OK) break;
-                int32_t *st = (int32_t *)(arena_p + s.status_off) + op * B;
-                uint32_t *ln = (uint32_t *)(arena_p + s.len_off) + op * B;
-                rc = lsb_plan_run(s.plan[op], op == LSB_OP_EMBED ? cfg->cover_pool : nullptr, arena_p,
-                                  op == LSB_OP_EMBED ? (uint8_t *)cfg->msg_pool : arena_p, ln, st, s.stream);
-                if (rc != LSB_OK) break;
-                hipError_t e = hipMemcpyAsync(s.status_host + op * B, st, sizeof(int32_t) * ids.size(),
-                                              hipMemcpyDeviceToHost, s.stream);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(s.len_host + op * B, ln, sizeof(uint32_t) * ids.size(), hipMemcpyDeviceToHost,
-                                       s.stream);
-                if (e != hipSuccess) rc = hip_fail(e, "lsb_serve: status copy");
             }
+            rc = ex.launch(s, jobs[0].data(), (int)slot_reqs[0][s].size(), jobs[1].data(),
+                           (int)slot_reqs[1][s].size());
             if (rc != LSB_OK) break;
-            hipError_t e = hipEventRecord(s.done, s.stream);
-            if (e != hipSuccess) {
-                rc = hip_fail(e, "lsb_serve: event record");
-                break;
-            }
-            s.busy = true;
+            busy[s] = true;
+            progressed = true;
             ++launches;
-            batched += (int64_t)(s.reqs[0].size() + s.reqs[1].size());
+            batched += (int64_t)(slot_reqs[0][s].size() + slot_reqs[1][s].size());
         }
 
         // ---- completions
-        for (Slot &s : slots) {
-            if (!s.busy || rc != LSB_OK) continue;
-            const hipError_t q = hipEventQuery(s.done);
-            if (q == hipErrorNotReady) continue;
-            if (q != hipSuccess) {
-                rc = hip_fail(q, "lsb_serve: event query");
-                break;
-            }
-            s.busy = false;
-            now = now_s();
+        for (int s = 0; s < S && rc == LSB_OK; ++s) {
+            if (!busy[s]) continue;
+            bool done = false;
+            rc = ex.poll(s, &done);
+            if (rc != LSB_OK || !done) continue;
+            busy[s] = false;
+            progressed = true;
+            now = ex.now();
             for (int op = 0; op < 2; ++op) {
-                for (size_t j = 0; j < s.reqs[op].size(); ++j) {
-                    const int i = s.reqs[op][j];
+                const std::vector<int> &ids = slot_reqs[op][s];
+                for (size_t j = 0; j < ids.size(); ++j) {
+                    const int i = ids[j];
                     lsb_result &r = res[i];
-                    r.status = s.status_host[op * B + j];
+                    r.status = ex.status(s, op, (int)j);
                     r.done_s = now;
                     ++finished;
                     last_done = now;
@@ -350,8 +454,8 @@ extern "C" int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *req, int 
                         }
                     } else {
                         const int t = (int)r.target;
-                        r.len = s.len_host[op * B + j];
-                        bytes += extract_bytes(req[t].n, res[t].len, res[t].k);
+                        r.len = ex.length(s, op, (int)j);
+                        bytes += extract_bytes(res[t].len, res[t].k);
                         if (!cfg->keep_outputs) {
                             release_out(i);  // message delivered
                             release_out(t);  // its stego is consumed
@@ -360,9 +464,8 @@ extern "C" int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *req, int 
                 }
             }
         }
+        if (!progressed && rc == LSB_OK) ex.idle(next < n_req ? req[next].arrival_s : 1e300);
     }
-
-    cleanup();
     if (rc != LSB_OK) return rc;
     if (stats) {
         memset(stats, 0, sizeof *stats);
@@ -389,4 +492,47 @@ extern "C" int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *req, int 
         stats->peak_arena_bytes = arena.peak();
     }
     return LSB_OK;
+}
+
+// Per-slot status arrays come out of the budget first (2 x B int32 + 2 x B
+// uint32 per slot).
+int reserve_status(const lsb_server_cfg *cfg, Arena &arena, std::vector<uint64_t> &st, std::vector<uint64_t> &ln) {
+    st.resize(cfg->n_slots);
+    ln.resize(cfg->n_slots);
+    for (int s = 0; s < cfg->n_slots; ++s)
+        if (!arena.alloc(sizeof(int32_t) * 2 * cfg->max_batch, &st[s]) ||
+            !arena.alloc(sizeof(uint32_t) * 2 * cfg->max_batch, &ln[s]))
+            return fail(LSB_E_NOMEM, "lsb_serve: arena too small for per-slot status arrays");
+    return LSB_OK;
+}
+
+}  // namespace
+
+extern "C" int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *req, int n_req, lsb_result *res,
+                         lsb_serve_stats *stats) {
+    clear_error();
+    int rc = check_args(cfg, req, n_req, res, true);
+    if (rc != LSB_OK) return rc;
+    Arena arena(cfg->arena_bytes);
+    std::vector<uint64_t> st, ln;
+    rc = reserve_status(cfg, arena, st, ln);
+    if (rc != LSB_OK) return rc;
+    HipExecutor ex(cfg, cfg->n_slots, cfg->max_batch);
+    rc = ex.init(st, ln);
+    if (rc != LSB_OK) return rc;
+    return run_scheduler(cfg, req, n_req, res, stats, ex, arena);
+}
+
+extern "C" int lsb_serve_simulate(const lsb_server_cfg *cfg, const lsb_request *req, int n_req, lsb_result *res,
+                                  lsb_serve_stats *stats, double launch_us, double device_gbps) {
+    clear_error();
+    int rc = check_args(cfg, req, n_req, res, false);
+    if (rc != LSB_OK) return rc;
+    if (!(launch_us >= 0) || !(device_gbps > 0)) return fail(LSB_E_ARG, "lsb_serve_simulate: bad timing model");
+    Arena arena(cfg->arena_bytes);
+    std::vector<uint64_t> st, ln;
+    rc = reserve_status(cfg, arena, st, ln);
+    if (rc != LSB_OK) return rc;
+    SimExecutor ex(cfg->n_slots, cfg->max_batch, launch_us, device_gbps);
+    return run_scheduler(cfg, req, n_req, res, stats, ex, arena);
 }

@@ -54,4 +54,19 @@ def serve(arena: torch.Tensor, cover_pool: torch.Tensor, msg_pool: torch.Tensor,
     return results, stats.as_dict()
 
 
-__all__ = ["REQ_DTYPE", "RES_DTYPE", "FREED", "poisson_requests", "serve"]
+def simulate(requests: np.ndarray, budget: int, max_batch: int = 256, n_slots: int = 4,
+             keep_outputs: bool = False, launch_us: float = 10.0, device_gbps: float = 5000.0):
+    """Run the serving scheduler on the host with modelled launches (no GPU,
+    no data): each launch takes launch_us plus its algorithmic bytes at
+    device_gbps.  Returns (results, stats) like serve()."""
+    requests = np.ascontiguousarray(requests, dtype=REQ_DTYPE)
+    results = np.zeros(requests.size, dtype=RES_DTYPE)
+    cfg = ServerCfg(None, int(budget), None, None, int(max_batch), int(n_slots), int(bool(keep_outputs)), 0)
+    stats = ServeStats()
+    check(lib().lsb_serve_simulate(ctypes.byref(cfg), ctypes.c_void_p(requests.ctypes.data), int(requests.size),
+                                   ctypes.c_void_p(results.ctypes.data), ctypes.byref(stats),
+                                   float(launch_us), float(device_gbps)))
+    return results, stats.as_dict()
+
+
+__all__ = ["REQ_DTYPE", "RES_DTYPE", "FREED", "poisson_requests", "serve", "simulate"]

@@ -1,0 +1,138 @@
+"""The serving scheduler on the host (lsb_serve_simulate): the same C++ loop
+as lsb_serve, with modelled launches on a virtual clock and no GPU.  Checks
+admission order, the HBM budget, eviction, extract targeting, continuous
+batching and rejection of requests that can never fit."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0912_0947_amd import serve
+from paper_0912_0947_amd._lib import E_NOMEM, OK, OP_EMBED, OP_EXTRACT
+from paper_0912_0947_amd.workloads import BatchWorkload
+
+
+@pytest.fixture(scope="module")
+def wl():
+    return BatchWorkload(256, oracle.capacity, seed=2101, lo=64, hi=2048)
+
+
+def _check_common(req, res, budget, stats):
+    n = len(req)
+    served = res["status"] == OK
+    # every request finished
+    assert np.all((res["status"] == OK) | (res["status"] == E_NOMEM))
+    # time order per request
+    ok = np.nonzero(served)[0]
+    assert np.all(res["admit_s"][ok] + 1e-12 >= req["arrival_s"][ok])
+    assert np.all(res["launch_s"][ok] >= res["admit_s"][ok])
+    assert np.all(res["done_s"][ok] >= res["launch_s"][ok])
+    # admission in arrival order
+    assert np.all(np.diff(res["admit_s"][ok]) >= 0)
+    # extracts read an embed that had finished, each stego at most once
+    ext = np.nonzero(served & (res["op_run"] == OP_EXTRACT))[0]
+    targets = res["target"][ext]
+    assert len(set(targets.tolist())) == len(targets)
+    for i in ext:
+        t = int(res[i]["target"])
+        assert 0 <= t < i and res[t]["op_run"] == OP_EMBED and res[t]["status"] == OK
+        assert res[t]["done_s"] <= res[i]["admit_s"] + 1e-12
+        assert res[i]["len"] == res[t]["len"] == req[t]["len"]
+    assert stats["peak_arena_bytes"] <= budget
+    assert stats["launches"] >= 1
+    assert 1 <= stats["mean_batch"]
+    return ok
+
+
+def test_large_budget_no_evictions(wl):
+    req, _ = serve.poisson_requests(wl, 10000.0, 3000, seed=2111)
+    budget = 64 << 30
+    res, stats = serve.simulate(req, budget, max_batch=64, n_slots=4)
+    ok = _check_common(req, res, budget, stats)
+    assert ok.size == len(req) and stats["evictions"] == 0 and stats["rejected"] == 0
+    assert stats["p99_ms"] >= stats["p50_ms"] > 0
+
+
+def test_continuous_batching_grows_with_load(wl):
+    """At low load each launch carries one request; at high load requests
+    that arrive while others run join the next launch."""
+    low, _ = serve.poisson_requests(wl, 500.0, 1000, seed=2121)
+    high, _ = serve.poisson_requests(wl, 200000.0, 1000, seed=2122)
+    _, s_low = serve.simulate(low, 64 << 30, max_batch=256, n_slots=1, launch_us=50.0, device_gbps=2000.0)
+    _, s_high = serve.simulate(high, 64 << 30, max_batch=256, n_slots=1, launch_us=50.0, device_gbps=2000.0)
+    assert s_low["mean_batch"] < 1.2
+    # one slot busy ~50 us per launch while 200k req/s arrive: ~10 per launch
+    assert s_high["mean_batch"] > 5 * s_low["mean_batch"]
+    assert s_high["p50_ms"] > s_low["p50_ms"]
+
+
+def test_tight_budget_evicts_oldest_and_stays_within(wl):
+    req, _ = serve.poisson_requests(wl, 50000.0, 2000, seed=2131, extract_frac=0.3)
+    budget = int(np.sort(wl.n)[-6:].sum()) + (1 << 20)
+    res, stats = serve.simulate(req, budget, max_batch=32, n_slots=4)
+    ok = _check_common(req, res, budget, stats)
+    assert ok.size == len(req)
+    assert stats["evictions"] > 0
+    # an evicted stego is gone (its offset released); one read by an extract
+    # was released after that extract finished
+    assert np.all(res["out_off"][res["op_run"] == OP_EXTRACT] == serve.FREED)
+
+
+def test_never_fitting_request_is_rejected_alone(wl):
+    req, _ = serve.poisson_requests(wl, 5000.0, 200, seed=2141, extract_frac=0.0)
+    big = int(np.argmax(req["n"]))
+    others = np.delete(np.arange(len(req)), big)
+    budget = int(req["n"][others].max()) + (1 << 16)
+    if budget >= req["n"][big]:
+        pytest.skip("largest request is not unique")
+    res, stats = serve.simulate(req, budget, max_batch=8, n_slots=2)
+    assert res[big]["status"] == E_NOMEM
+    assert np.all(res["status"][others] == OK)
+    assert stats["rejected"] == 1
+
+
+def test_keep_outputs_never_frees(wl):
+    req, _ = serve.poisson_requests(wl, 20000.0, 400, seed=2151)
+    res, stats = serve.simulate(req, 64 << 30, max_batch=16, n_slots=3, keep_outputs=True)
+    assert np.all(res["status"] == OK)
+    assert np.all(res["out_off"] != serve.FREED)
+    offs = res["out_off"].astype(np.int64)
+    sizes = np.where(res["op_run"] == OP_EMBED, req["n"], res["len"]).astype(np.int64)
+    order = np.argsort(offs)
+    ends = offs[order] + sizes[order]
+    assert np.all(ends[:-1] <= offs[order][1:]), "two kept outputs overlap in the arena"
+
+
+def test_deterministic(wl):
+    req, _ = serve.poisson_requests(wl, 30000.0, 800, seed=2161)
+    a, sa = serve.simulate(req, 1 << 30, max_batch=32, n_slots=3)
+    b, sb = serve.simulate(req, 1 << 30, max_batch=32, n_slots=3)
+    assert np.array_equal(a, b) and sa == sb
+
+
+def test_explicit_targets_and_fallback_to_embed(wl):
+    """An extract naming an embed that is resident reads it; one naming a
+    request whose stego is not resident (never embedded) is served as an
+    embed."""
+    req, _ = serve.poisson_requests(wl, 1000.0, 6, seed=2171, extract_frac=0.0)
+    req["arrival_s"] = [0.0, 0.001, 0.002, 0.003, 0.004, 0.005]
+    req["op"][3] = OP_EXTRACT
+    req["target"][3] = 1
+    req["op"][4] = OP_EXTRACT
+    req["target"][4] = 3  # request 3 is an extract: nothing resident to read
+    res, stats = serve.simulate(req, 64 << 30, max_batch=4, n_slots=1)
+    assert res[3]["op_run"] == OP_EXTRACT and res[3]["target"] == 1
+    assert res[4]["op_run"] == OP_EMBED and res[4]["target"] == -1
+
+
+def test_argument_errors(wl):
+    req, _ = serve.poisson_requests(wl, 1000.0, 10, seed=2181)
+    bad = req.copy()
+    bad["arrival_s"][5] = 0.0  # unsorted
+    with pytest.raises(Exception):
+        serve.simulate(bad, 1 << 30)
+    bad = req.copy()
+    bad["target"][3] = 7  # points forward
+    with pytest.raises(Exception):
+        serve.simulate(bad, 1 << 30)
+    with pytest.raises(Exception):
+        serve.simulate(req, 1 << 30, max_batch=0)
