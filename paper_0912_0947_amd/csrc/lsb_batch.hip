@@ -68,6 +68,26 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// One tile of a job: ranges with k known at compile time, then the walk
+// over the tile's vectors.
+template <int K, int UNR, bool NT>
+__device__ __forceinline__ void embed_tile(const Span &s, uint64_t v_begin, uint64_t tile_vectors, uint32_t wave,
+                                           uint32_t n_waves, uint32_t lane) {
+    const Ranges r = embed_ranges<K>(s);
+    uint64_t v_end = v_begin + tile_vectors;
+    if (v_end > r.count) v_end = r.count;
+    if (v_begin < v_end) embed_walk<K, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane);
+}
+
+template <int K, int UNR, bool NT>
+__device__ __forceinline__ void extract_tile(const Span &s, uint64_t v_begin, uint64_t tile_vectors, uint32_t wave,
+                                             uint32_t n_waves, uint32_t lane) {
+    const Ranges r = extract_ranges<K>(s);
+    uint64_t v_end = v_begin + tile_vectors;
+    if (v_end > r.count) v_end = r.count;
+    if (v_begin < v_end) extract_walk<K, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane);
+}
+
 template <int UNR, bool NT>
 __device__ __forceinline__ void run_tile(const DevJob &J, uint64_t v_begin, uint64_t tile_vectors,
                                          const uint8_t *cover_arena, uint8_t *stego_arena, uint8_t *msg_arena,
@@ -84,37 +104,29 @@ __device__ __forceinline__ void run_tile(const DevJob &J, uint64_t v_begin, uint
         s.body = msg_arena + J.msg_off;
         s.bits = 8 * (4 + (uint64_t)J.len);
         s.hdr = J.len;
-        const Ranges r = embed_ranges(s);
-        uint64_t v_end = v_begin + tile_vectors;
-        if (v_end > r.count) v_end = r.count;
-        if (v_begin >= v_end) return;
         switch (J.k) {
-            case 1: embed_walk<1, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
-            case 2: embed_walk<2, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
-            case 3: embed_walk<3, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
-            case 4: embed_walk<4, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
-            case 5: embed_walk<5, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
-            case 6: embed_walk<6, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
-            case 7: embed_walk<7, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
-            default: embed_walk<8, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+            case 1: embed_tile<1, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 2: embed_tile<2, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 3: embed_tile<3, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 4: embed_tile<4, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 5: embed_tile<5, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 6: embed_tile<6, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 7: embed_tile<7, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            default: embed_tile<8, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
         }
     } else {
         s.src = stego_arena + J.stego_off;
         s.out = msg_arena + J.msg_off;
         s.bits = 8 * (4 + (uint64_t)len);
-        const Ranges r = extract_ranges(s);
-        uint64_t v_end = v_begin + tile_vectors;
-        if (v_end > r.count) v_end = r.count;
-        if (v_begin >= v_end) return;
         switch (J.k) {
-            case 1: extract_walk<1, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
-            case 2: extract_walk<2, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
-            case 3: extract_walk<3, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
-            case 4: extract_walk<4, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
-            case 5: extract_walk<5, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
-            case 6: extract_walk<6, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
-            case 7: extract_walk<7, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
-            default: extract_walk<8, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane); break;
+            case 1: extract_tile<1, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 2: extract_tile<2, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 3: extract_tile<3, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 4: extract_tile<4, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 5: extract_tile<5, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 6: extract_tile<6, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 7: extract_tile<7, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            default: extract_tile<8, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
         }
     }
 }

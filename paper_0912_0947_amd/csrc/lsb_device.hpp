@@ -62,9 +62,13 @@ __host__ __device__ inline uint64_t stream_byte0(const Span &s) {
     return ((uint64_t)s.k * s.t0) >> 3;  // stream byte holding field t0's first bit
 }
 
+// The range functions take k as a compile-time constant on the device
+// (KC > 0), so that their divisions by k and 2k become shifts or constant
+// multiplies instead of 64-bit division sequences; KC = 0 reads s.k (host).
+template <int KC = 0>
 __host__ __device__ inline Ranges embed_ranges(const Span &s) {
     Ranges r;
-    const uint64_t k = (uint64_t)s.k;
+    const uint64_t k = KC > 0 ? (uint64_t)KC : (uint64_t)s.k;
     const uint64_t full = s.bits / k;            // fields fully inside the stream
     const uint64_t any = ceil_div(s.bits, k);    // fields carrying any stream bit
     const uint64_t whole = s.n / 16;             // vectors fully inside the buffer
@@ -80,9 +84,10 @@ __host__ __device__ inline Ranges embed_ranges(const Span &s) {
 }
 
 // For extract, s.bits is the end bit e <= k*(t0+n), and k*t0 % 8 == 0.
+template <int KC = 0>
 __host__ __device__ inline Ranges extract_ranges(const Span &s) {
     Ranges r;
-    const uint64_t k = (uint64_t)s.k;
+    const uint64_t k = KC > 0 ? (uint64_t)KC : (uint64_t)s.k;
     const uint64_t full = s.bits / k;
     const uint64_t whole = s.n / 16;
     const uint64_t sb = stream_byte0(s);
@@ -271,8 +276,10 @@ __device__ __forceinline__ void store_chunk_words(uint8_t *p, const uint32_t *w)
 // Per-byte forms used for edge vectors and for misaligned buffers.
 
 // Embed buffer byte t.  Writes nothing for a copy-only byte of an in-place span.
+// KC > 0 fixes k at compile time (as in the range functions); 0 reads s.k.
+template <int KC = 0>
 __device__ __forceinline__ void embed_byte(const Span &s, uint64_t t) {
-    const uint32_t k = (uint32_t)s.k;
+    const uint32_t k = KC > 0 ? (uint32_t)KC : (uint32_t)s.k;
     const uint64_t first = (uint64_t)k * (s.t0 + t);
     const uint32_t c = s.src[t];
     if (first >= s.bits) {
@@ -296,8 +303,9 @@ __device__ __forceinline__ void embed_byte(const Span &s, uint64_t t) {
 // Compute logical stream byte i (which must start at or after field t0 and
 // before the span's end bit s.bits) from the stego bytes; bits at or past
 // s.bits read as zero.
+template <int KC = 0>
 __device__ __forceinline__ uint32_t extract_stream_byte(const Span &s, uint64_t i) {
-    const uint32_t k = (uint32_t)s.k;
+    const uint32_t k = KC > 0 ? (uint32_t)KC : (uint32_t)s.k;
     const uint32_t low = (1u << k) - 1u;
     const uint64_t b0 = 8 * i;
     const uint64_t b1 = (b0 + 8 < s.bits) ? b0 + 8 : s.bits;  // exclusive, > b0
@@ -369,7 +377,7 @@ __device__ __forceinline__ void embed_walk(const Span &s, const Ranges &r, uint6
                     if (!s.inplace) store16<NT>(s.dst + 16 * u, load16<NT>(s.src + 16 * u));
                 } else {
                     const uint64_t t_end = 16 * u + 16 < s.n ? 16 * u + 16 : s.n;
-                    for (uint64_t t = 16 * u; t < t_end; ++t) embed_byte(s, t);
+                    for (uint64_t t = 16 * u; t < t_end; ++t) embed_byte<K>(s, t);
                 }
             }
         }
@@ -472,7 +480,7 @@ __device__ __forceinline__ void extract_walk(const Span &s, const Ranges &r, uin
                     const uint64_t end_byte = ceil_div(s.bits, 8);
                     for (uint64_t i = i0; i < i0 + 2 * K && i < end_byte; ++i) {
                         if (i < s.hdr_len) continue;
-                        s.out[i - s.hdr_len] = (uint8_t)extract_stream_byte(s, i);
+                        s.out[i - s.hdr_len] = (uint8_t)extract_stream_byte<K>(s, i);
                     }
                 }
             }

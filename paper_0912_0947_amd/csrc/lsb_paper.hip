@@ -15,7 +15,29 @@
 #include "lsb_host.hpp"
 #include "lsb_paper_device.hpp"
 
+namespace lsb {
+
+// One block per row; dynamic LDS holds the row's data chunk.  C > 0 fixes
+// the channel count at compile time (1, 3, 4), 0 reads it from the span.
+template <int C>
+__global__ void __launch_bounds__(256) lsb_paper_embed_rows_kernel(PaperSpan p) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t paper_chunk[];
+    const PaperRow r = paper_row(p, blockIdx.x);
+    if (r.L == 0) {
+        if (!p.inplace) paper_row_copy(p, r, threadIdx.x, blockDim.x);
+        return;
+    }
+    paper_row_stage(p, r, paper_chunk, threadIdx.x, blockDim.x);
+    __syncthreads();
+    paper_row_update<C>(p, r, paper_chunk, threadIdx.x, blockDim.x);
+}
+
+}  // namespace lsb
+
 using namespace lsb;
+
+// Largest data chunk per row staged in LDS by the row kernel.
+static constexpr uint64_t kPaperRowChunkMax = 60 * 1024;
 
 static int paper_check(uint32_t h, uint32_t w, uint32_t c, uint32_t plane, uint64_t len, const char *who) {
     if (c == 0 || plane >= c) return fail(LSB_E_ARG, "%s: plane %u outside 0..%u", who, plane, c ? c - 1 : 0);
@@ -55,7 +77,24 @@ int lsb_paper_embed(const uint8_t *cover, uint8_t *stego, uint32_t h, uint32_t w
     p.q = w / 4;
     p.inplace = cover == stego;
     if (p.rowbytes >= (1ull << 31)) return fail(LSB_E_ARG, "lsb_paper_embed: rows of 2^31 bytes or more");
-    const bool vec = (((uintptr_t)cover | (uintptr_t)stego) & 15u) == 0 && p.rowbytes >= 16;
+    const bool aligned = (((uintptr_t)cover | (uintptr_t)stego) & 15u) == 0;
+    if (aligned && p.rowbytes % 16 == 0 && p.q + 4 <= kPaperRowChunkMax && h < (1u << 31)) {
+        // rows past the last data-carrying one: copied out-of-place, untouched in-place
+        const uint64_t rows_with_data = p.q ? ceil_div(len, p.q) : 0;
+        const uint64_t rows = p.inplace ? rows_with_data : h;
+        if (rows == 0) return LSB_OK;
+        const size_t lds = (size_t)((p.q + 3 + 15) / 16 * 16);
+        hipEvent_t e0, e1;
+        take_launch_events(&e0, &e1);
+        void (*fn)(PaperSpan) = c == 1 ? lsb_paper_embed_rows_kernel<1>
+                                : c == 3 ? lsb_paper_embed_rows_kernel<3>
+                                : c == 4 ? lsb_paper_embed_rows_kernel<4>
+                                         : lsb_paper_embed_rows_kernel<0>;
+        hipExtLaunchKernelGGL(fn, dim3((unsigned)rows), dim3(256), lds, (hipStream_t)stream, e0, e1, 0, p);
+        const hipError_t e = hipGetLastError();
+        return e == hipSuccess ? LSB_OK : hip_fail(e, "paper row embed kernel launch");
+    }
+    const bool vec = aligned && p.rowbytes >= 16;
     const uint64_t items = vec ? ceil_div(n, 16) : n;
     uint64_t blocks = ceil_div(items, 256);
     const uint64_t cap = (uint64_t)device_cus() * 16;

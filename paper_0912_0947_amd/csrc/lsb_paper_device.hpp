@@ -139,6 +139,115 @@ __global__ void __launch_bounds__(256) lsb_paper_embed_kernel(PaperSpan p) {
     }
 }
 
+// -------------------------------------------------------------------------
+// Row-per-block embed.  Block y handles image row y: it stages the row's data
+// chunk (data bytes [y*q, y*q + L)) in LDS with dword loads, then each lane
+// streams 16-byte vectors of the row and rewrites their plane bytes from LDS
+// (Section VI steps 5-7).  No 64-bit division and no scattered global gathers.
+// Used when the row length is a multiple of 16, both image pointers are
+// 16-byte aligned and the chunk fits the block's LDS.
+
+struct PaperRow {
+    const uint8_t *src;
+    uint8_t *dst;
+    uint64_t first;  // first data byte of the row
+    uint32_t L;      // data bytes of the row (0: the row carries none)
+    uint32_t h0;     // (data + first) % 4: LDS offset of data byte `first`
+};
+
+__device__ __forceinline__ PaperRow paper_row(const PaperSpan &p, uint64_t y) {
+    PaperRow r;
+    r.src = p.src + y * p.rowbytes;
+    r.dst = p.dst + y * p.rowbytes;
+    r.first = y * p.q;
+    const uint64_t left = r.first < p.len ? p.len - r.first : 0;
+    r.L = left < p.q ? (uint32_t)left : p.q;
+    r.h0 = (uint32_t)((uintptr_t)(p.data + r.first) & 3u);
+    return r;
+}
+
+// Copy a row that carries no data (out-of-place only).
+__device__ __forceinline__ void paper_row_copy(const PaperSpan &p, const PaperRow &r, uint32_t tid, uint32_t nthreads) {
+    const uint32_t rowvecs = (uint32_t)(p.rowbytes / 16);
+    for (uint32_t u = tid; u < rowvecs; u += nthreads) store16<true>(r.dst + 16 * (uint64_t)u, load16<true>(r.src + 16 * (uint64_t)u));
+}
+
+// Stage data bytes [first, first + L) at chunk[h0 .. h0 + L): whole dwords
+// of the data buffer land on aligned LDS dwords; the partial dwords at the
+// two ends are copied byte by byte, so no byte outside the chunk is read.
+__device__ __forceinline__ void paper_row_stage(const PaperSpan &p, const PaperRow &r, uint8_t *chunk, uint32_t tid,
+                                                uint32_t nthreads) {
+    const uint8_t *a = p.data + r.first;
+    const uint32_t *aw = reinterpret_cast<const uint32_t *>(a - r.h0);
+    const uint32_t end = r.h0 + r.L;
+    const uint32_t nw = (end + 3) / 4;
+    for (uint32_t w = tid; w < nw; w += nthreads) {
+        const uint32_t lo = 4 * w;
+        if (lo >= r.h0 && lo + 4 <= end) {
+            reinterpret_cast<uint32_t *>(chunk)[w] = aw[w];
+        } else {
+            for (uint32_t b = lo; b < lo + 4; ++b)
+                if (b >= r.h0 && b < end) chunk[b] = a[b - r.h0];
+        }
+    }
+}
+
+// New value of the 16 row bytes at row offset o (Section VI step 7): for a
+// plane byte of pixel x < 4L, i = x / L (by three compares) and j = x - i*L;
+// its low two bits become bits 2i+1..2i of data byte j (data = the staged
+// chunk, data[j] = data byte first + j).  All 16 LDS reads are issued before
+// any is used; bytes that take no data read data[0] and keep their value.
+template <int C>
+__device__ __forceinline__ u32x4 paper_row_vec(const PaperSpan &p, const uint8_t *data, uint32_t L, uint32_t o,
+                                               u32x4 v) {
+    const uint32_t c = C > 0 ? (uint32_t)C : p.c;
+    uint32_t x = o / c;
+    uint32_t ch = o - x * c;
+    const uint32_t four_l = 4 * L;
+    bool need[16];
+    uint32_t shift[16], d[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        need[k] = ch == p.plane && x < four_l;
+        const uint32_t i = (x >= L) + (x >= 2 * L) + (x >= 3 * L);
+        shift[k] = 2 * i;
+        d[k] = data[need[k] ? x - i * L : 0];
+        const bool wrap = ch + 1 == c;
+        ch = wrap ? 0 : ch + 1;
+        x = wrap ? x + 1 : x;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int sh = 8 * (k & 3);
+        const uint32_t nv = (v[k >> 2] & ~(3u << sh)) | (((d[k] >> shift[k]) & 3u) << sh);
+        v[k >> 2] = need[k] ? nv : v[k >> 2];
+    }
+    return v;
+}
+
+// This lane's vectors of a data-carrying row: UNR loads in flight, then the
+// updates and stores.
+template <int C>
+__device__ __forceinline__ void paper_row_update(const PaperSpan &p, const PaperRow &r, const uint8_t *chunk,
+                                                 uint32_t tid, uint32_t nthreads) {
+    constexpr int UNR = 4;
+    const uint32_t rowvecs = (uint32_t)(p.rowbytes / 16);
+    const uint8_t *data = chunk + r.h0;
+    for (uint32_t base = tid; base < rowvecs; base += UNR * nthreads) {
+        u32x4 v[UNR];
+#pragma unroll
+        for (int m = 0; m < UNR; ++m) {
+            const uint32_t u = base + m * nthreads;
+            if (u < rowvecs) v[m] = load16<true>(r.src + 16 * (uint64_t)u);
+        }
+#pragma unroll
+        for (int m = 0; m < UNR; ++m) {
+            const uint32_t u = base + m * nthreads;
+            if (u < rowvecs) store16<true>(r.dst + 16 * (uint64_t)u, paper_row_vec<C>(p, data, r.L, 16 * u, v[m]));
+        }
+    }
+}
+
 // Extract: one lane per data byte d; row y = d / q holds bytes
 // [y*q, y*q + L); byte j of the row is ORed together from the low two bits
 // of pixels L*i + j, shifted left by 2i (Section VII step 6).

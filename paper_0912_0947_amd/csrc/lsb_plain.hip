@@ -26,12 +26,16 @@ namespace lsb {
 // Vector embed over the whole span; grid-stride over wave groups.
 template <int K, int UNR, bool NT>
 __global__ void __launch_bounds__(1024) lsb_embed_kernel(Span s) {
-    const Ranges r = embed_ranges(s);
+    const Ranges r = embed_ranges<K>(s);
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     embed_walk<K, UNR, NT>(s, r, 0, r.count, wave, n_waves, lane);
 }
+
+__device__ uint8_t header_dummy = 0;  // global (not constant) address space: the loads stay global_load
+constexpr int kMaxUnroll = 4;
+__device__ __attribute__((aligned(16))) uint8_t group_dummy[16 * 64 * kMaxUnroll] = {};
 
 // Vector extract.  header != 0: decode the length on the device, report it
 // and the status through block 0, and extract the message; header == 0: raw
@@ -40,6 +44,7 @@ template <int K, int UNR, bool NT, bool BALLOT>
 __global__ void __launch_bounds__(1024)
     lsb_extract_kernel(Span s, int header, uint64_t out_cap, uint32_t *len_out, int32_t *status_out) {
     constexpr uint64_t G = 64 * UNR;
+    static_assert(UNR <= kMaxUnroll, "the dummy group holds kMaxUnroll*64 vectors");
     // ballot packing stages 1 KiB per wave (16 waves per block at most)
     __shared__ __attribute__((aligned(16))) uint8_t stage_all[BALLOT ? 16 * 1024 : 16];
     uint8_t *stage = BALLOT ? stage_all + 1024 * (threadIdx.x >> 6) : nullptr;
@@ -47,24 +52,32 @@ __global__ void __launch_bounds__(1024)
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     if (!header) {
-        const Ranges r = extract_ranges(s);
+        const Ranges r = extract_ranges<K>(s);
         extract_walk<K, UNR, NT, BALLOT>(s, r, 0, r.count, wave, n_waves, lane, stage);
         return;
     }
-    // Header mode.  Lane j < 32 reads the stego byte holding stream bit j;
-    // while that load is in flight the wave already loads its first group
-    // of stego vectors whenever the group lies inside the buffer (the loads
-    // do not depend on the decoded length).
+    // Header mode.  Lane j reads the stego byte holding stream bit j % 32
+    // (a wave-uniform branch, so the load is issued first), then the wave
+    // loads its first group of stego vectors, which do not depend on the
+    // decoded length: the header's memory latency overlaps the group's.  A
+    // wave whose first group lies past the buffer loads group 0 instead and
+    // drops it.
     const bool fits = (uint64_t)K * s.n >= 32;
-    uint32_t hbyte = 0;
-    if (fits && lane < 32) hbyte = s.src[lane / K];
     const uint64_t u_first = wave * G;
     const bool pre = (u_first + G) * 16 <= s.n;
+    // Branch-free: a buffer too short for a header reads a dummy byte.
+    const uint8_t *hp = fits ? s.src + (lane & 31u) / K : &header_dummy;
+    const uint32_t hbyte = *hp;
+    asm volatile("" ::: "memory");
+    // The loads are unconditional (no merge of register values after them):
+    // a buffer smaller than one group reads the dummy group instead.  The
+    // compiler barriers keep the header load first and stop the group loads
+    // from being sunk below the decode into the block that consumes them.
+    const uint8_t *gp = s.n >= 16 * G ? s.src + 16 * (pre ? u_first : 0) : group_dummy;
     u32x4 c[UNR];
-    if (pre) {
 #pragma unroll
-        for (int j = 0; j < UNR; ++j) c[j] = load16<NT>(s.src + 16 * (u_first + (uint64_t)j * 64 + lane));
-    }
+    for (int j = 0; j < UNR; ++j) c[j] = load16<NT>(gp + 16 * ((uint64_t)j * 64 + lane));
+    asm volatile("" ::: "memory");
     uint32_t len = 0;
     int status = LSB_E_HEADER;
     if (fits) {
@@ -80,7 +93,7 @@ __global__ void __launch_bounds__(1024)
     }
     if (status != LSB_OK) return;
     s.bits = 8 * (4 + (uint64_t)len);
-    const Ranges r = extract_ranges(s);
+    const Ranges r = extract_ranges<K>(s);
     uint64_t v_begin = 0;
     if (pre && u_first >= r.fast_begin && u_first + G <= r.fast_end && u_first + G <= r.count) {
         if constexpr (BALLOT && K == 1)

@@ -155,7 +155,7 @@ __device__ __forceinline__ u32x4 plane_gather_any(const u32x4 *v, uint32_t plane
 // bytes, partial field, pixel tail) go field by field.
 template <int K, int C>
 __global__ void __launch_bounds__(256) lsb_plane_embed_vec_kernel(Span s, uint32_t plane) {
-    const Ranges r = embed_ranges(s);
+    const Ranges r = embed_ranges<K>(s);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uintptr_t body_base = (uintptr_t)s.body - s.hdr_len;  // stream byte i at body_base + i
     for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < r.count; u += stride) {
@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(256)
     }
     if (status != LSB_OK) return;
     s.bits = 8 * (4 + (uint64_t)len);
-    const Ranges r = extract_ranges(s);
+    const Ranges r = extract_ranges<K>(s);
     const uintptr_t out_base = (uintptr_t)s.out - s.hdr_len;
     const uint64_t end_byte = ceil_div(s.bits, 8);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;

@@ -43,7 +43,7 @@ __device__ __forceinline__ uint32_t bytes_differ(u32x4 a, u32x4 b) {
 // s.src = cover, s.dst = stego (read only here).
 template <int K>
 __global__ void __launch_bounds__(256) lsb_verify_kernel(Span s, unsigned long long *mismatches) {
-    const Ranges r = embed_ranges(s);  // inplace = 0: every vector is visited
+    const Ranges r = embed_ranges<K>(s);  // inplace = 0: every vector is visited
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uintptr_t body_base = (uintptr_t)s.body - s.hdr_len;
     uint32_t bad = 0;

@@ -43,6 +43,44 @@ def test_random_shapes(seed):
     assert_bytes_equal(to_host(buf), want, "paper embed in place")
 
 
+@pytest.mark.parametrize("seed", range(20))
+def test_row_kernel_shapes(seed):
+    """Rows of a multiple of 16 bytes with 16-byte aligned image pointers take
+    the row-per-block kernel: every channel count 1..5, a data pointer at each
+    offset mod 4, a partial last data row, no data, and in-place."""
+    g = inputs.rng(1331, seed)
+    c = 1 + seed % 5
+    w = 16 * int(g.integers(1, 80))
+    h = int(g.integers(1, 120))
+    plane = int(g.integers(0, c))
+    cap = oracle.paper_capacity(h, w)
+    ln = [cap, int(g.integers(1, cap + 1)), 0, int(g.integers(0, w // 4 + 1))][seed % 4]
+    cover = inputs.random_bytes(h * w * c, 1332, seed)
+    data = inputs.random_bytes(ln, 1333, seed)
+    rc, want = oracle.paper_embed(cover, h, w, c, plane, data)
+    assert rc == 0
+    dm = seed % 4
+    st = api.paper_embed(to_dev(cover), h, w, c, plane, to_dev(data, pad_before=dm, pad_after=3))
+    assert_bytes_equal(to_host(st), want, "row kernel h=%d w=%d c=%d plane=%d len=%d dm=%d" % (h, w, c, plane, ln, dm))
+    buf = to_dev(cover)
+    api.paper_embed(buf, h, w, c, plane, to_dev(data, pad_before=3 - dm), out=buf)  # in place
+    assert_bytes_equal(to_host(buf), want, "row kernel in place")
+    assert_bytes_equal(to_host(api.paper_extract(st, h, w, c, plane, ln)), data, "row kernel extract")
+
+
+def test_wide_rows_fall_back():
+    """A row whose data chunk exceeds the row kernel's staging limit takes the
+    per-vector kernel (w = 262,144 pixels: 65,536 data bytes per row)."""
+    h, w, c = 3, 262144, 1
+    cap = oracle.paper_capacity(h, w)
+    ln = cap - 1000
+    cover = inputs.random_bytes(h * w * c, 1341)
+    data = inputs.random_bytes(ln, 1342)
+    rc, want = oracle.paper_embed(cover, h, w, c, 0, data)
+    st = api.paper_embed(to_dev(cover), h, w, c, 0, to_dev(data))
+    assert_bytes_equal(to_host(st), want, "wide rows")
+
+
 def test_session_shape():
     """Section VIII: 56 bytes into a 1024x1 row."""
     cover = inputs.random_bytes(1024, 1311)
