@@ -196,6 +196,66 @@ def bench_paper_layout(api, lib_handle, cover, dev, reps=5):
     return res
 
 
+# launch shapes (block, vectors in flight per lane, grid; 0 = one pass) swept
+# for the reference streams
+REF_SHAPES = [(256, 1, 0), (512, 1, 0), (1024, 1, 0), (256, 2, 0), (256, 1, 1024), (256, 2, 512),
+              (512, 2, 256), (256, 2, 1024), (1024, 1, 256), (256, 4, 512), (512, 4, 256)]
+
+
+def bench_ceiling(api, lib_handle, srcs, dsts, dev, reps=7):
+    """Achievable bandwidth for the traffic mixes of the k = 1 embed (read n
+    + n/8, write n) and extract (read n, write n/8) on this device: plain
+    hand-written streams of the same bytes over the rotating buffer sets, the
+    best of REF_SHAPES, each shape the median of ``reps`` launches timed with
+    launch-bound events."""
+    import torch
+
+    from paper_0912_0947_amd import inputs
+    from paper_0912_0947_amd._lib import REF_COPY, REF_EMBED_MIX, REF_EXTRACT_MIX
+
+    n = srcs[0].numel()
+    sides = [torch.empty(n // 8, dtype=torch.uint8, device=dev) for _ in srcs]
+    for i, t in enumerate(sides):
+        inputs.fill_uniform(t, 1801 + i)
+    smalls = [torch.empty(n // 8, dtype=torch.uint8, device=dev) for _ in srcs]
+    kinds = [("copy", REF_COPY, 2 * n), ("embed_k1_mix", REF_EMBED_MIX, 2 * n + n // 8),
+             ("extract_k1_mix", REF_EXTRACT_MIX, n + n // 8)]
+    out = {}
+    it = 0
+    for name, kind, b in kinds:
+        best = None
+        for block, unroll, grid in REF_SHAPES:
+            ms = []
+            for r in range(reps + 1):
+                j = it % len(srcs)
+                it += 1
+                dst = smalls[j] if kind == REF_EXTRACT_MIX else dsts[j]
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                e1.record()
+                torch.cuda.synchronize()
+                lib_handle.lsb_time_next_launch(e0, e1)
+                api.stream_reference(kind, srcs[j], dst, sides[j] if kind == REF_EMBED_MIX else None,
+                                     block=block, unroll=unroll, grid=grid)
+                torch.cuda.synchronize()
+                if r:
+                    ms.append(e0.elapsed_time(e1))
+            us = statistics.median(ms) * 1e3
+            if best is None or us < best["us_median"]:
+                best = {"bytes": b, "us_median": round(us, 2), "GBps": round(b / (us * 1e-6) / 1e9, 1),
+                        "shape": {"block": block, "unroll": unroll, "grid": grid}}
+        out[name] = best
+    # the streams really moved the bytes: spot-check the last embed-mix output
+    j = (it - 1) % len(srcs)
+    api.stream_reference(REF_EMBED_MIX, srcs[j], dsts[j], sides[j])
+    v = dsts[j][:4096].view(torch.int32).view(-1, 4)
+    w = srcs[j][:4096].view(torch.int32).view(-1, 4).clone()
+    w[:, 0] ^= sides[j][:512].view(torch.int16).to(torch.int32) & 0xFFFF
+    assert torch.equal(v, w), "reference stream output mismatch"
+    del sides, smalls
+    return out
+
+
 def bench_quality(api, lib_handle, cover, stego_by_k, msgs_by_k, dev, reps=5):
     """Section VIII's quality figure on the large image: PSNR of each stego
     against its cover over all bytes, from the device squared-error kernel
@@ -508,6 +568,11 @@ def main():
     }
     result["paper_layout"] = bench_paper_layout(api, L, covers[0], dev)
     result["quality"] = bench_quality(api, L, covers[0], {k: stegos[k][1] for k in KS}, msgs, dev)
+    log("reference streams ...")
+    ceil = bench_ceiling(api, L, covers, stegos[1], dev)
+    ceil["embed_k1_of_ceiling"] = round(ceil["embed_k1_mix"]["us_median"] / per["embed_k1"]["us_median"], 4)
+    ceil["extract_k1_of_ceiling"] = round(ceil["extract_k1_mix"]["us_median"] / per["extract_k1"]["us_median"], 4)
+    result["stream_ceiling"] = ceil
 
     if not args.no_batched:
         from paper_0912_0947_amd import batch, serve

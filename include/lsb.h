@@ -330,12 +330,34 @@ typedef struct lsb_serve_stats {
 int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *requests, int n_requests, lsb_result *results,
               lsb_serve_stats *stats);
 
-/* Measurement support: the next plain embed or extract kernel launched by
- * the calling thread records `start_event` and `stop_event` (hipEvent_t
+/* Measurement support: the next kernel launched by an embed, extract,
+ * paper-layout, plane, squared-error, verify or reference-stream call of the
+ * calling thread records `start_event` and `stop_event` (hipEvent_t
  * handles passed as void*, created with timing enabled) at the kernel's own
  * begin and end, so that per-launch durations exclude queueing and marker
  * packets.  Applies to one launch, then clears.  Both may be NULL to clear. */
 int lsb_time_next_launch(void *start_event, void *stop_event);
+
+/* Measurement support: reference streams with the traffic mixes of the
+ * method's kernels, so that a kernel's duration can be set against a plain
+ * stream of the same bytes on the same device.  Computes nothing of the
+ * method.  Over the nv = n / 16 vectors of 16 bytes of `src`:
+ *   LSB_REF_COPY         dst vector i = src vector i       (read n, write n)
+ *   LSB_REF_EMBED_MIX    as COPY with 16-bit side[i] XORed into the first
+ *                        dword (read n + n/8, write n: the k = 1 embed mix)
+ *   LSB_REF_EXTRACT_MIX  16-bit dst[i] = low half of the XOR of src vector
+ *                        i's four dwords (read n, write n/8: the k = 1
+ *                        extract mix); side unused
+ * n must be a multiple of 16; src (and dst for the first two kinds) 16-byte
+ * aligned, side and dst 2-byte aligned; dst holds n bytes (n/8 for
+ * EXTRACT_MIX) and overlaps no input.  Launch shape: block in {256, 512,
+ * 1024}, unroll in {1, 2, 4} vectors in flight per lane (one grid stride
+ * apart), grid 0 = enough blocks for one pass, else capped at that.  Device
+ * pointers, asynchronous on `stream`; timed like the embed kernel through
+ * lsb_time_next_launch.  Errors: LSB_E_ARG. */
+enum { LSB_REF_COPY = 0, LSB_REF_EMBED_MIX = 1, LSB_REF_EXTRACT_MIX = 2 };
+int lsb_stream_reference(int kind, const uint8_t *src, uint8_t *dst, const uint8_t *side, uint64_t n, int block,
+                         int unroll, uint32_t grid, void *stream);
 
 /* The same scheduler without a GPU: launches are modelled (a launch of
  * jobs moving B algorithmic bytes finishes launch_us + B / device_gbps after

@@ -27,9 +27,15 @@ __global__ void __launch_bounds__(256) lsb_paper_embed_rows_kernel(PaperSpan p) 
         if (!p.inplace) paper_row_copy(p, r, threadIdx.x, blockDim.x);
         return;
     }
-    paper_row_stage(p, r, paper_chunk, threadIdx.x, blockDim.x);
+    paper_row_stage(p, r, paper_chunk + kPaperGuard, threadIdx.x, blockDim.x);
     __syncthreads();
-    paper_row_update<C>(p, r, paper_chunk, threadIdx.x, blockDim.x);
+    if constexpr (C == 1 || C == 3 || C == 4) {
+        if (r.L >= PaperWindow<C>::len) {
+            paper_row_update<C, true>(p, r, paper_chunk, threadIdx.x, blockDim.x);
+            return;
+        }
+    }
+    paper_row_update<C, false>(p, r, paper_chunk, threadIdx.x, blockDim.x);
 }
 
 }  // namespace lsb
@@ -38,6 +44,7 @@ using namespace lsb;
 
 // Largest data chunk per row staged in LDS by the row kernel.
 static constexpr uint64_t kPaperRowChunkMax = 60 * 1024;
+static_assert(paper_row_lds_bytes(kPaperRowChunkMax) <= 64 * 1024, "row kernel LDS within 64 KiB");
 
 static int paper_check(uint32_t h, uint32_t w, uint32_t c, uint32_t plane, uint64_t len, const char *who) {
     if (c == 0 || plane >= c) return fail(LSB_E_ARG, "%s: plane %u outside 0..%u", who, plane, c ? c - 1 : 0);
@@ -83,7 +90,7 @@ int lsb_paper_embed(const uint8_t *cover, uint8_t *stego, uint32_t h, uint32_t w
         const uint64_t rows_with_data = p.q ? ceil_div(len, p.q) : 0;
         const uint64_t rows = p.inplace ? rows_with_data : h;
         if (rows == 0) return LSB_OK;
-        const size_t lds = (size_t)((p.q + 3 + 15) / 16 * 16);
+        const size_t lds = (size_t)paper_row_lds_bytes(p.q);
         hipEvent_t e0, e1;
         take_launch_events(&e0, &e1);
         void (*fn)(PaperSpan) = c == 1 ? lsb_paper_embed_rows_kernel<1>

@@ -225,14 +225,124 @@ __device__ __forceinline__ u32x4 paper_row_vec(const PaperSpan &p, const uint8_t
     return v;
 }
 
-// This lane's vectors of a data-carrying row: UNR loads in flight, then the
-// updates and stores.
+// Window form for c = 1, 3, 4.  The plane bytes of a 16-byte vector are
+// the pixels xf, xf + 1, ... (16, 5 or 6, 4 of them), so their data bytes
+// are a contiguous run of the chunk, read with a few LDS dwords and a funnel
+// shift.  With L >= the window length a window meets at most one quarter
+// boundary: pixels before it take bit pair i of data[j0 + m], pixels after
+// it bit pair i + 1 of data[m - ms] (ms = L - j0 pixels remain in quarter
+// i), read as a second window starting L bytes earlier.  Pixels at or past
+// 4L take no data.  LDS holds kPaperGuard readable bytes before the chunk
+// and 32 after it, so both windows stay inside the allocation.
+constexpr uint32_t kPaperGuard = 16;
+
 template <int C>
-__device__ __forceinline__ void paper_row_update(const PaperSpan &p, const PaperRow &r, const uint8_t *chunk,
+struct PaperWindow {
+    static constexpr uint32_t len = C == 1 ? 16 : (C == 3 ? 6 : 4);  // plane pixels read per vector
+};
+
+__device__ __forceinline__ uint32_t funnel8(uint32_t hi, uint32_t lo, uint32_t s) {
+    return (uint32_t)((((uint64_t)hi << 32) | lo) >> (8 * s));
+}
+
+// Bytes chunk[a .. a + 4*NW) as NW dwords (little-endian), a >= 0 relative
+// to the 4-byte aligned chunk base.
+template <int NW>
+__device__ __forceinline__ void lds_window(const uint8_t *chunk, uint32_t a, uint32_t *out) {
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(chunk) + (a >> 2);
+    const uint32_t s = a & 3u;
+    uint32_t d[NW + 1];
+#pragma unroll
+    for (int t = 0; t <= NW; ++t) d[t] = w[t];
+#pragma unroll
+    for (int t = 0; t < NW; ++t) out[t] = funnel8(d[t + 1], d[t], s);
+}
+
+// Data-bit pairs and keep masks (0x03 per byte that takes data) of the
+// window's pixels, packed one per byte in NW dwords.
+template <int NW>
+__device__ __forceinline__ void paper_pairs(const uint8_t *chunk, uint32_t h0, uint32_t L, uint32_t xf,
+                                            uint32_t *pairs, uint32_t *keep) {
+    const bool any = xf < 4 * L;
+    const uint32_t i = (xf >= L) + (xf >= 2 * L) + (xf >= 3 * L);
+    const uint32_t j0 = any ? xf - i * L : 0;
+    const uint32_t ms = L - j0;  // >= 1: window pixels still in quarter i
+    const bool cross = ms < 4 * NW;
+    const bool next = cross && i < 3;  // pixels after the boundary take quarter i + 1
+    uint32_t a[NW], b[NW];
+    lds_window<NW>(chunk, kPaperGuard + h0 + j0, a);
+    lds_window<NW>(chunk, kPaperGuard + h0 + j0 - (cross ? L : 0), b);
+#pragma unroll
+    for (int t = 0; t < NW; ++t) {
+        // bytes of dword t below ms come from window a
+        const uint32_t lo = ms >= 4u * t + 4 ? 0xFFFFFFFFu : (ms <= 4u * t ? 0u : (1u << (8 * (ms - 4 * t))) - 1u);
+        const uint32_t pa = (a[t] >> (2 * i)) & 0x03030303u;
+        const uint32_t pb = (b[t] >> (2 * (i + 1) & 7)) & 0x03030303u;
+        const uint32_t hi_ok = next ? ~lo : 0u;
+        pairs[t] = any ? (pa & lo) | (pb & hi_ok) : 0u;
+        keep[t] = any ? 0x03030303u & (lo | hi_ok) : 0u;
+    }
+}
+
+// 128-bit value t shifted left by r bytes (r < 4), dword 0 lowest.
+__device__ __forceinline__ void shl_bytes(uint32_t *t, uint32_t r) {
+    const uint32_t sh = 32 - 8 * r;
+#pragma unroll
+    for (int d = 3; d >= 0; --d) t[d] = (uint32_t)((((uint64_t)t[d] << 32) | (d ? t[d - 1] : 0u)) >> sh);
+}
+
+// Six packed bytes (bytes 0..3 of p0, 0..1 of p1) to bytes 0, 3, 6, 9, 12,
+// 15 of a 128-bit value, then shifted left by r bytes.
+__device__ __forceinline__ void spread3(uint32_t p0, uint32_t p1, uint32_t r, uint32_t *t) {
+    t[0] = (p0 & 0xFFu) | ((p0 & 0xFF00u) << 16);
+    t[1] = p0 & 0xFF0000u;
+    t[2] = (p0 >> 16) & 0xFF00u;
+    t[3] = (p1 & 0xFFu) | ((p1 & 0xFF00u) << 16);
+    shl_bytes(t, r);
+}
+
+template <int C>
+__device__ __forceinline__ u32x4 paper_row_vec_window(const PaperSpan &p, const uint8_t *chunk, uint32_t h0,
+                                                      uint32_t L, uint32_t o, u32x4 v) {
+    if constexpr (C == 1) {
+        uint32_t pr[4], kp[4];
+        paper_pairs<4>(chunk, h0, L, o, pr, kp);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) v[d] = (v[d] & ~kp[d]) | pr[d];
+    } else if constexpr (C == 3) {
+        const uint32_t ch0 = o % 3u;
+        const uint32_t r = (p.plane + 3u - ch0) % 3u;  // first plane byte of the vector
+        const uint32_t xf = (o + r) / 3u;
+        uint32_t pr[2], kp[2], tp[4], tk[4];
+        paper_pairs<2>(chunk, h0, L, xf, pr, kp);
+        spread3(pr[0], pr[1], r, tp);
+        spread3(kp[0], kp[1], r, tk);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) v[d] = (v[d] & ~tk[d]) | tp[d];
+    } else {
+        static_assert(C == 4, "window form for c = 1, 3, 4");
+        const uint32_t sh = 8 * p.plane;  // o % 4 == 0: byte `plane` of each dword
+        uint32_t pr[1], kp[1];
+        paper_pairs<1>(chunk, h0, L, o / 4u, pr, kp);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const uint32_t pd = ((pr[0] >> (8 * d)) & 3u) << sh, kd = ((kp[0] >> (8 * d)) & 3u) << sh;
+            v[d] = (v[d] & ~kd) | pd;
+        }
+    }
+    return v;
+}
+
+// This lane's vectors of a data-carrying row: UNR loads in flight, then the
+// updates and stores.  `lds` is the block's LDS area: kPaperGuard bytes,
+// then the staged chunk.  WIN selects the window form (c = 1, 3, 4 and
+// L >= its window length, a block-uniform choice).
+template <int C, bool WIN>
+__device__ __forceinline__ void paper_row_update(const PaperSpan &p, const PaperRow &r, const uint8_t *lds,
                                                  uint32_t tid, uint32_t nthreads) {
     constexpr int UNR = 4;
     const uint32_t rowvecs = (uint32_t)(p.rowbytes / 16);
-    const uint8_t *data = chunk + r.h0;
+    const uint8_t *data = lds + kPaperGuard + r.h0;
     for (uint32_t base = tid; base < rowvecs; base += UNR * nthreads) {
         u32x4 v[UNR];
 #pragma unroll
@@ -243,10 +353,18 @@ __device__ __forceinline__ void paper_row_update(const PaperSpan &p, const Paper
 #pragma unroll
         for (int m = 0; m < UNR; ++m) {
             const uint32_t u = base + m * nthreads;
-            if (u < rowvecs) store16<true>(r.dst + 16 * (uint64_t)u, paper_row_vec<C>(p, data, r.L, 16 * u, v[m]));
+            if (u >= rowvecs) continue;
+            u32x4 w;
+            if constexpr (WIN) w = paper_row_vec_window<C>(p, lds, r.h0, r.L, 16 * u, v[m]);
+            else w = paper_row_vec<C>(p, data, r.L, 16 * u, v[m]);
+            store16<true>(r.dst + 16 * (uint64_t)u, w);
         }
     }
 }
+
+// LDS bytes of the row kernel for rows of q data bytes: guard, chunk (with
+// the data pointer's offset mod 4), and the window reads' overrun.
+__host__ __device__ constexpr uint64_t paper_row_lds_bytes(uint64_t q) { return kPaperGuard + (q + 3 + 32 + 15) / 16 * 16; }
 
 // Extract: one lane per data byte d; row y = d / q holds bytes
 // [y*q, y*q + L); byte j of the row is ORed together from the low two bits

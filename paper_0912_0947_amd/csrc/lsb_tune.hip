@@ -76,7 +76,7 @@ extern "C" int lsb_autotune(int op, int k, uint64_t n, uint8_t *cover, uint8_t *
     }
     const int blocks[] = {256, 512, 1024};
     const int unrolls[] = {1, 2, 4};
-    const int caps[] = {0, 2, 4, 8, 16};
+    const int caps[] = {0, 1, 2, 4, 8, 16};
     double best_t = 1e30;
     lsb_launch_cfg best_c = tune_lookup(op, k, n);
     const int packs = (op == LSB_OP_EXTRACT && k == 1) ? 2 : 1;  // ballot packing exists for k = 1

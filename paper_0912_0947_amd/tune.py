@@ -19,6 +19,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tune_gfx950.json")
 SIZES = [1 << 12, 1 << 14, 1 << 16, 1 << 18, 786432, 1 << 21, 6220800, 1 << 24, 1 << 26, 201326592, 1 << 29]
 KS = range(1, 9)
+# Sizes from here up are timed in steady state over rotating buffer sets
+# (their working set exceeds the 256 MB last-level cache); smaller ones by
+# lsb_autotune after a cache flush.
+ROTATE_MIN = 1 << 26
+ROT_SETS = 3
+BLOCKS, UNROLLS, CAPS = (256, 512, 1024), (1, 2, 4), (0, 1, 2, 4, 8, 16)
 
 
 def bucket(n: int) -> int:
@@ -60,6 +66,55 @@ def load(handle=None, path: str = TABLE) -> bool:
     return True
 
 
+def tune_rotating(op: int, k: int, n: int, sets, reps: int = 7):
+    """Steady-state choice for one (op, k, n): every candidate launch shape is
+    launched ``reps`` times over the buffer sets in turn, each launch timed by
+    events bound to the kernel itself; the lowest median wins and is installed
+    for n's bucket.  ``sets`` holds (cover, stego, msg, out, len_status) per
+    set; every stego already carries a full-capacity stream."""
+    import statistics
+
+    import torch
+
+    from . import api
+    from ._lib import lib
+
+    L = lib()
+    cap = api.capacity(n, k)
+    packs = (0, 1) if (op == api.OP_EXTRACT and k == 1) else (0,)
+    best = None
+    it = 0
+    for pack in packs:
+        for nt in (0, 1):
+            for block in BLOCKS:
+                for unroll in UNROLLS:
+                    for capb in CAPS:
+                        api.tune_set(op, k, bucket(n), block, unroll, capb, nt, pack)
+                        ms = []
+                        for r in range(reps + 1):
+                            cover, stego, msg, out, ls = sets[it % len(sets)]
+                            it += 1
+                            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                            e0.record()
+                            e1.record()
+                            torch.cuda.synchronize()
+                            L.lsb_time_next_launch(e0, e1)
+                            if op == api.OP_EMBED:
+                                api.embed(cover[:n], msg[:cap], k, out=stego[:n])
+                            else:
+                                api.extract(stego[:n], k, out=out[:cap], len_status=ls)
+                            torch.cuda.synchronize()
+                            if r:
+                                ms.append(e0.elapsed_time(e1))
+                        us = statistics.median(ms) * 1e3
+                        if best is None or us < best[1]:
+                            best = ({"block": block, "unroll": unroll, "blocks_per_cu": capb, "nontemporal": nt,
+                                     "pack": pack}, us)
+    c = best[0]
+    api.tune_set(op, k, bucket(n), c["block"], c["unroll"], c["blocks_per_cu"], c["nontemporal"], c["pack"])
+    return best
+
+
 def tune_plain(reps: int = 5, sizes=SIZES, ks=KS, log=print):
     import torch
 
@@ -67,19 +122,50 @@ def tune_plain(reps: int = 5, sizes=SIZES, ks=KS, log=print):
 
     dev = torch.device("cuda:0")
     entries = []
-    biggest = max(sizes)
-    cover = torch.empty(biggest, dtype=torch.uint8, device=dev)
-    stego = torch.empty(biggest, dtype=torch.uint8, device=dev)
-    msg = torch.empty(biggest, dtype=torch.uint8, device=dev)
-    inputs.fill_uniform(cover, 11)
-    inputs.fill_uniform(msg, 12)
-    for n in sizes:
-        for k in ks:
-            cap = api.capacity(n, k)
-            for op in (api.OP_EMBED, api.OP_EXTRACT):
-                cfg, us = api.autotune(op, k, cover[:n], stego[:n], msg[:cap], reps=reps)
-                entries.append({"op": op, "k": k, "bucket": bucket(n), "n": n, "cfg": cfg, "us": round(us, 2)})
-                log("op=%d k=%d n=%d -> %s %.1f us" % (op, k, n, cfg, us))
+    small = [n for n in sizes if n < ROTATE_MIN]
+    large = [n for n in sizes if n >= ROTATE_MIN]
+    if small:
+        biggest = max(small)
+        cover = torch.empty(biggest, dtype=torch.uint8, device=dev)
+        stego = torch.empty(biggest, dtype=torch.uint8, device=dev)
+        msg = torch.empty(biggest, dtype=torch.uint8, device=dev)
+        inputs.fill_uniform(cover, 11)
+        inputs.fill_uniform(msg, 12)
+        for n in small:
+            for k in ks:
+                cap = api.capacity(n, k)
+                for op in (api.OP_EMBED, api.OP_EXTRACT):
+                    cfg, us = api.autotune(op, k, cover[:n], stego[:n], msg[:cap], reps=reps)
+                    entries.append({"op": op, "k": k, "bucket": bucket(n), "n": n, "cfg": cfg, "us": round(us, 2),
+                                    "method": "flush"})
+                    log("op=%d k=%d n=%d -> %s %.1f us" % (op, k, n, cfg, us))
+        del cover, stego, msg
+    if large:
+        biggest = max(large)
+        sets = []
+        for j in range(ROT_SETS):
+            cover = torch.empty(biggest, dtype=torch.uint8, device=dev)
+            msg = torch.empty(biggest, dtype=torch.uint8, device=dev)
+            inputs.fill_uniform(cover, 13 + j)
+            inputs.fill_uniform(msg, 23 + j)
+            sets.append((cover, torch.empty(biggest, dtype=torch.uint8, device=dev), msg,
+                         torch.empty(biggest, dtype=torch.uint8, device=dev),
+                         torch.zeros(2, dtype=torch.int32, device=dev)))
+        for n in large:
+            for k in ks:
+                cap = api.capacity(n, k)
+                for cover, stego, msg, _, _ in sets:  # stegos carry full-capacity streams
+                    api.embed(cover[:n], msg[:cap], k, out=stego[:n])
+                for op in (api.OP_EMBED, api.OP_EXTRACT):
+                    cfg, us = tune_rotating(op, k, n, sets, reps=max(reps, 7))
+                    entries.append({"op": op, "k": k, "bucket": bucket(n), "n": n, "cfg": cfg, "us": round(us, 2),
+                                    "method": "rotating"})
+                    log("op=%d k=%d n=%d -> %s %.1f us (rotating)" % (op, k, n, cfg, us))
+                # the extracts above must have returned every message
+                for cover, stego, msg, out, ls in sets:
+                    st = ls.cpu().tolist()
+                    assert st == [cap, 0], (op, k, n, st)
+        del sets
     return entries
 
 
