@@ -150,47 +150,160 @@ __device__ __forceinline__ u32x4 plane_gather_any(const u32x4 *v, uint32_t plane
     return u32x4{0u, 0u, 0u, 0u};
 }
 
-// Embed over the plane view; s.n = pixels, s.src/s.dst the interleaved
-// cover/stego (16-byte aligned), header mode (t0 = 0).  Edge vectors (header
-// bytes, partial field, pixel tail) go field by field.
+// Wave groups: a wave takes 64 consecutive 16-pixel units (64*C vectors,
+// C KiB of the interleaved buffer).  When the whole group is fast, the wave
+// loads it with C contiguous 1 KiB accesses into LDS, each lane reads back
+// its own C vectors (16 pixels), and, for embed, the results go back through
+// LDS to C contiguous stores: every global access of the wave covers one
+// contiguous span, instead of 64 lanes touching C-vector runs at a stride of
+// 16*C bytes.  Other groups (header, stream end, buffer tail) go lane by lane.
+
+// stage[64*i + lane] = vector 64*i + lane of the group.
+template <int C>
+__device__ __forceinline__ void plane_group_load(const uint8_t *src, u32x4 *stage, uint32_t lane) {
+#pragma unroll
+    for (int i = 0; i < C; ++i) stage[64 * i + lane] = load16<true>(src + 16 * (64 * i + lane));
+}
+
+template <int C>
+__device__ __forceinline__ void plane_group_store(uint8_t *dst, const u32x4 *stage, uint32_t lane) {
+#pragma unroll
+    for (int i = 0; i < C; ++i) store16<true>(dst + 16 * (64 * i + lane), stage[64 * i + lane]);
+}
+
+// Embed unit u (16 pixels) whose C vectors are in stage[C*lane .. C*lane + C).
 template <int K, int C>
-__global__ void __launch_bounds__(256) lsb_plane_embed_vec_kernel(Span s, uint32_t plane) {
-    const Ranges r = embed_ranges<K>(s);
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+__device__ __forceinline__ void plane_group_embed(const Span &s, u32x4 *stage, uint64_t u, uint32_t lane,
+                                                  uint32_t plane) {
     const uintptr_t body_base = (uintptr_t)s.body - s.hdr_len;  // stream byte i at body_base + i
-    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < r.count; u += stride) {
-        uint8_t *dst = s.dst + 16 * C * u;
-        const uint8_t *src = s.src + 16 * C * u;
-        if (u >= r.fast_begin && u < r.fast_end) {
-            u32x4 v[C];
+    u32x4 v[C];
 #pragma unroll
-            for (int i = 0; i < C; ++i) v[i] = load16<true>(src + 16 * i);
-            uint32_t w[Chunk<K>::NW];
-            const uint8_t *p = reinterpret_cast<const uint8_t *>(body_base + 2 * K * u);
-            if (s.words) load_chunk_words<K>(p, w);
-            else load_chunk_bytes<K>(p, 0, w);
-            plane_embed_vec_any<K, C>(v, w, plane);
+    for (int i = 0; i < C; ++i) v[i] = stage[C * lane + i];
+    uint32_t w[Chunk<K>::NW];
+    const uint8_t *p = reinterpret_cast<const uint8_t *>(body_base + 2 * K * u);
+    if (s.words) load_chunk_words<K>(p, w);
+    else load_chunk_bytes<K>(p, 0, w);
+    plane_embed_vec_any<K, C>(v, w, plane);
 #pragma unroll
-            for (int i = 0; i < C; ++i) store16<true>(dst + 16 * i, v[i]);
-        } else if (u >= r.copy_begin && u < r.copy_end) {
-            if (!s.inplace) {
+    for (int i = 0; i < C; ++i) stage[C * lane + i] = v[i];
+}
+
+// One unit lane by lane (groups that are not wholly fast).
+template <int K, int C>
+__device__ __forceinline__ void plane_embed_unit(const Span &s, const Ranges &r, uint64_t u, uint32_t plane) {
+    uint8_t *dst = s.dst + 16 * C * u;
+    const uint8_t *src = s.src + 16 * C * u;
+    if (u >= r.fast_begin && u < r.fast_end) {
+        const uintptr_t body_base = (uintptr_t)s.body - s.hdr_len;
+        u32x4 v[C];
 #pragma unroll
-                for (int i = 0; i < C; ++i) store16<true>(dst + 16 * i, load16<true>(src + 16 * i));
-            }
-        } else {
-            const uint64_t px_end = 16 * u + 16 < s.n ? 16 * u + 16 : s.n;
-            for (uint64_t px = 16 * u; px < px_end; ++px) {
-                if (!s.inplace)
-                    for (uint32_t ch = 0; ch < (uint32_t)C; ++ch)
-                        if (ch != plane) s.dst[px * C + ch] = s.src[px * C + ch];
-                const uint64_t at = plane_byte(px, C, plane);
-                if ((uint64_t)s.k * px >= s.bits) {
-                    if (!s.inplace) s.dst[at] = s.src[at];
-                } else {
-                    plane_embed_field(s, px, C, plane);
-                }
+        for (int i = 0; i < C; ++i) v[i] = load16<true>(src + 16 * i);
+        uint32_t w[Chunk<K>::NW];
+        const uint8_t *p = reinterpret_cast<const uint8_t *>(body_base + 2 * K * u);
+        if (s.words) load_chunk_words<K>(p, w);
+        else load_chunk_bytes<K>(p, 0, w);
+        plane_embed_vec_any<K, C>(v, w, plane);
+#pragma unroll
+        for (int i = 0; i < C; ++i) store16<true>(dst + 16 * i, v[i]);
+    } else if (u >= r.copy_begin && u < r.copy_end) {
+        if (!s.inplace) {
+#pragma unroll
+            for (int i = 0; i < C; ++i) store16<true>(dst + 16 * i, load16<true>(src + 16 * i));
+        }
+    } else {
+        const uint64_t px_end = 16 * u + 16 < s.n ? 16 * u + 16 : s.n;
+        for (uint64_t px = 16 * u; px < px_end; ++px) {
+            if (!s.inplace)
+                for (uint32_t ch = 0; ch < (uint32_t)C; ++ch)
+                    if (ch != plane) s.dst[px * C + ch] = s.src[px * C + ch];
+            const uint64_t at = plane_byte(px, C, plane);
+            if ((uint64_t)s.k * px >= s.bits) {
+                if (!s.inplace) s.dst[at] = s.src[at];
+            } else {
+                plane_embed_field(s, px, C, plane);
             }
         }
+    }
+}
+
+// Group classes (wave-uniform).
+enum PlaneGroup { PLANE_FAST = 0, PLANE_COPY = 1, PLANE_EDGE = 2 };
+
+__device__ __forceinline__ int plane_group_class(const Ranges &r, uint64_t u0) {
+    if (u0 >= r.fast_begin && u0 + 64 <= r.fast_end) return PLANE_FAST;
+    if (u0 >= r.copy_begin && u0 + 64 <= r.copy_end) return PLANE_COPY;
+    return PLANE_EDGE;
+}
+
+// Embed over the plane view; s.n = pixels, s.src/s.dst the interleaved
+// cover/stego (16-byte aligned), header mode (t0 = 0).
+template <int K, int C>
+__global__ void __launch_bounds__(256) lsb_plane_embed_vec_kernel(Span s, uint32_t plane) {
+    __shared__ u32x4 stage_all[4][64 * C];  // one stage per wave of the 256-thread block
+    const Ranges r = embed_ranges<K>(s);
+    const uint32_t lane = threadIdx.x & 63u;
+    u32x4 *stage = stage_all[threadIdx.x >> 6];
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    const uint64_t groups = ceil_div(r.count, 64);
+    for (uint64_t g = wave; g < groups; g += n_waves) {
+        const uint64_t u0 = 64 * g;
+        const int cls = plane_group_class(r, u0);
+        if (cls == PLANE_FAST) {
+            plane_group_load<C>(s.src + 16 * C * u0, stage, lane);
+            __builtin_amdgcn_wave_barrier();
+            plane_group_embed<K, C>(s, stage, u0 + lane, lane, plane);
+            __builtin_amdgcn_wave_barrier();
+            plane_group_store<C>(s.dst + 16 * C * u0, stage, lane);
+            __builtin_amdgcn_wave_barrier();
+        } else if (cls == PLANE_COPY) {
+            if (!s.inplace) {
+#pragma unroll
+                for (int i = 0; i < C; ++i)
+                    store16<true>(s.dst + 16 * (C * u0 + 64 * i + lane), load16<true>(s.src + 16 * (C * u0 + 64 * i + lane)));
+            }
+        } else if (u0 + lane < r.count) {
+            plane_embed_unit<K, C>(s, r, u0 + lane, plane);
+        }
+    }
+}
+
+// Extract unit u from its C vectors v (fast units).
+template <int K, int C>
+__device__ __forceinline__ void plane_extract_vec_out(const Span &s, const u32x4 *v, uint64_t u, uint32_t plane) {
+    const uintptr_t out_base = (uintptr_t)s.out - s.hdr_len;
+    uint32_t w[Chunk<K>::NW];
+    extract_vec<K>(plane_gather_any<K, C>(v, plane), w);
+    uint8_t *p = reinterpret_cast<uint8_t *>(out_base + 2 * K * u);
+    if (s.words) {
+        store_chunk_words<K>(p, w);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 2 * K; ++i) p[i] = (uint8_t)(w[i >> 2] >> (24 - 8 * (i & 3)));
+    }
+}
+
+template <int K, int C>
+__device__ __forceinline__ void plane_group_extract(const Span &s, const u32x4 *stage, uint64_t u, uint32_t lane,
+                                                    uint32_t plane) {
+    u32x4 v[C];
+#pragma unroll
+    for (int i = 0; i < C; ++i) v[i] = stage[C * lane + i];
+    plane_extract_vec_out<K, C>(s, v, u, plane);
+}
+
+template <int K, int C>
+__device__ __forceinline__ void plane_extract_unit(const Span &s, const Ranges &r, uint64_t u, uint32_t plane) {
+    if (u >= r.fast_begin && u < r.fast_end) {
+        u32x4 v[C];
+#pragma unroll
+        for (int i = 0; i < C; ++i) v[i] = load16<true>(s.src + 16 * (C * u + i));
+        plane_extract_vec_out<K, C>(s, v, u, plane);
+    } else {
+        const uint64_t end_byte = ceil_div(s.bits, 8);
+        const uint64_t i0 = 2 * K * u;
+        for (uint64_t i = i0; i < i0 + 2 * K && i < end_byte; ++i)
+            if (i >= s.hdr_len) s.out[i - s.hdr_len] = (uint8_t)plane_stream_byte(s, i, C, plane);
     }
 }
 
@@ -199,6 +312,7 @@ __global__ void __launch_bounds__(256) lsb_plane_embed_vec_kernel(Span s, uint32
 template <int K, int C>
 __global__ void __launch_bounds__(256)
     lsb_plane_extract_vec_kernel(Span s, uint32_t plane, uint64_t out_cap, uint32_t *len_out, int32_t *status_out) {
+    __shared__ u32x4 stage_all[4][64 * C];
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t len = 0;
     int status = LSB_E_HEADER;
@@ -217,27 +331,19 @@ __global__ void __launch_bounds__(256)
     if (status != LSB_OK) return;
     s.bits = 8 * (4 + (uint64_t)len);
     const Ranges r = extract_ranges<K>(s);
-    const uintptr_t out_base = (uintptr_t)s.out - s.hdr_len;
-    const uint64_t end_byte = ceil_div(s.bits, 8);
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < r.count; u += stride) {
-        if (u >= r.fast_begin && u < r.fast_end) {
-            u32x4 v[C];
-#pragma unroll
-            for (int i = 0; i < C; ++i) v[i] = load16<true>(s.src + 16 * (C * u + i));
-            uint32_t w[Chunk<K>::NW];
-            extract_vec<K>(plane_gather_any<K, C>(v, plane), w);
-            uint8_t *p = reinterpret_cast<uint8_t *>(out_base + 2 * K * u);
-            if (s.words) {
-                store_chunk_words<K>(p, w);
-            } else {
-#pragma unroll
-                for (int i = 0; i < 2 * K; ++i) p[i] = (uint8_t)(w[i >> 2] >> (24 - 8 * (i & 3)));
-            }
-        } else {
-            const uint64_t i0 = 2 * K * u;
-            for (uint64_t i = i0; i < i0 + 2 * K && i < end_byte; ++i)
-                if (i >= s.hdr_len) s.out[i - s.hdr_len] = (uint8_t)plane_stream_byte(s, i, C, plane);
+    u32x4 *stage = stage_all[threadIdx.x >> 6];
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    const uint64_t groups = ceil_div(r.count, 64);
+    for (uint64_t g = wave; g < groups; g += n_waves) {
+        const uint64_t u0 = 64 * g;
+        if (plane_group_class(r, u0) == PLANE_FAST) {
+            plane_group_load<C>(s.src + 16 * C * u0, stage, lane);
+            __builtin_amdgcn_wave_barrier();
+            plane_group_extract<K, C>(s, stage, u0 + lane, lane, plane);
+            __builtin_amdgcn_wave_barrier();
+        } else if (u0 + lane < r.count) {
+            plane_extract_unit<K, C>(s, r, u0 + lane, plane);
         }
     }
 }

@@ -51,6 +51,35 @@ def test_plane_random(k, seed):
     assert_bytes_equal(to_host(buf), want, "plane embed in place")
 
 
+@pytest.mark.parametrize("c", [2, 3, 4])
+@pytest.mark.parametrize("seed", range(8))
+def test_plane_vector_kernels(c, seed):
+    """The vector kernels (aligned buffers, 2-4 channels): many wave groups of
+    1024 pixels, a ragged tail, every k and plane, messages at each offset
+    mod 4, full and partial capacity, in place and out of place."""
+    k = 1 + seed
+    g = inputs.rng(1611, c, seed)
+    plane = seed % c
+    pixels = int(g.integers(1024 * 3, 1024 * 60)) + int(g.integers(0, 1024))
+    cap = oracle.capacity(pixels, k)
+    ln = cap if seed % 2 == 0 else int(g.integers(cap // 3, cap))
+    cover = inputs.random_bytes(pixels * c, 1612, c, seed)
+    msg = inputs.random_bytes(ln, 1613, c, seed)
+    rc, want = oracle.embed_plane(cover, c, plane, msg, k)
+    assert rc == 0
+    mo = seed % 4
+    st = api.embed_plane(to_dev(cover), c, plane, to_dev(msg, pad_before=mo, pad_after=3), k)
+    assert_bytes_equal(to_host(st), want, "plane vec embed k=%d c=%d plane=%d pixels=%d" % (k, c, plane, pixels))
+    out = empty_dev(ln + 64, pad_before=(mo + 1) % 4)
+    _, ls = api.extract_plane(st, c, plane, k, out=out)
+    ls = ls.cpu().numpy()
+    assert ls[1] == OK and ls[0] == ln
+    assert_bytes_equal(to_host(out)[:ln], msg, "plane vec extract")
+    buf = to_dev(cover)
+    api.embed_plane(buf, c, plane, to_dev(msg), k, out=buf)
+    assert_bytes_equal(to_host(buf), want, "plane vec embed in place")
+
+
 def test_plane_status_codes():
     pixels, c, k = 3000, 3, 2
     cap = oracle.capacity(pixels, k)
