@@ -57,7 +57,7 @@ enum {
     LSB_E_NOMEM = -6     /* a plan or graph could not be allocated */
 };
 
-enum { LSB_OP_EMBED = 0, LSB_OP_EXTRACT = 1 };
+enum { LSB_OP_EMBED = 0, LSB_OP_EXTRACT = 1, LSB_OP_MIXED = 2 };
 
 /* Message capacity in bytes of an n-byte cover at k bits per byte:
  * floor(n*k/8) - 4, capped at 2^32 - 1 by the header width (Section VI step 5
@@ -201,24 +201,30 @@ typedef struct lsb_job {
     uint64_t msg_cap;   /* extract: output capacity in bytes (embed: unused) */
     uint32_t len;       /* embed: message length (extract: unused)           */
     uint8_t k;          /* bits per cover byte, 1..8                         */
-    uint8_t op;         /* LSB_OP_EMBED or LSB_OP_EXTRACT                    */
+    uint8_t op;         /* LSB_OP_EMBED or LSB_OP_EXTRACT (LSB_OP_MIXED plans) */
     uint16_t reserved;  /* must be 0                                         */
 } lsb_job;              /* 48 bytes */
 
 typedef struct lsb_plan lsb_plan;
 
-/* Create a plan for up to max_jobs jobs.  Allocates device and pinned host
- * memory (this is the only allocating call of the batched form).  The plan
- * owns a HIP graph {job-table upload, prologue kernel, persistent kernel}
- * captured on the first run and reused afterwards. */
-int lsb_plan_create(lsb_plan **plan, int max_jobs);
+/* Create a plan for n_jobs jobs (1 <= n_jobs <= 2^24).  Allocates device and
+ * pinned host memory (this is the only allocating call of the batched form).
+ * The plan owns a HIP graph {job-table upload, prologue kernel, persistent
+ * kernel} captured on the first run and reused afterwards.
+ *   jobs_host  host array of n_jobs jobs, or NULL to reserve room for n_jobs
+ *              jobs and set them later with lsb_plan_update.
+ *   op         LSB_OP_EMBED or LSB_OP_EXTRACT: every job of the plan is of
+ *              that kind (the jobs' own op fields are ignored);
+ *              LSB_OP_MIXED: each job's op field says which it is.
+ * On error *plan is NULL and nothing is left allocated. */
+int lsb_plan_create(lsb_plan **plan, const lsb_job *jobs_host, int n_jobs, int op);
 
-/* Replace the plan's job list (n_jobs <= max_jobs).  Validates every job on
- * the host: a job with bad k or offsets is LSB_E_ARG for the whole call; an
- * embed job whose len exceeds its capacity is not an error of the call: it
- * gets status LSB_E_CAPACITY and no work.  Must not be called while a run of
- * this plan is still in flight on a stream (the upload reads the host copy). */
-int lsb_plan_set_jobs(lsb_plan *plan, const lsb_job *jobs, int n_jobs);
+/* Replace the plan's job list (n_jobs <= the n_jobs given at creation),
+ * keeping its graph.  Validates every job on the host: a job with bad k or
+ * offsets is LSB_E_ARG for the whole call; an embed job whose len exceeds its
+ * capacity is not an error of the call: it gets status LSB_E_CAPACITY and no
+ * work.  Waits for the plan's previous run to have read the job table. */
+int lsb_plan_update(lsb_plan *plan, const lsb_job *jobs_host, int n_jobs);
 
 /* Run every job of the plan on `stream`.  For job j: status_dev[j] <- LSB_OK
  * or its error; for extract jobs len_dev[j] <- decoded length (len_dev may
@@ -227,6 +233,20 @@ int lsb_plan_set_jobs(lsb_plan *plan, const lsb_job *jobs, int n_jobs);
 int lsb_plan_run(lsb_plan *plan, const uint8_t *cover_arena,
                  uint8_t *stego_arena, uint8_t *msg_arena, uint32_t *len_dev,
                  int32_t *status_dev, void *stream);
+
+/* lsb_plan_run for a plan whose jobs are all embeds (LSB_E_ARG otherwise):
+ * job j reads cover_arena + cover_off and msg_arena + msg_off, writes
+ * stego_arena + stego_off and status_dev[j]. */
+int lsb_embed_batch(lsb_plan *plan, const uint8_t *cover_arena,
+                    uint8_t *stego_arena, const uint8_t *msg_arena,
+                    int32_t *status_dev, void *stream);
+
+/* lsb_plan_run for a plan whose jobs are all extracts (LSB_E_ARG otherwise):
+ * job j reads stego_arena + stego_off, writes msg_arena + msg_off (at most
+ * msg_cap bytes), len_dev[j] and status_dev[j]. */
+int lsb_extract_batch(lsb_plan *plan, const uint8_t *stego_arena,
+                      uint8_t *msg_arena, uint32_t *len_dev,
+                      int32_t *status_dev, void *stream);
 
 /* Total tiles (work units) of the current job list, for reporting. */
 int64_t lsb_plan_tiles(const lsb_plan *plan);

@@ -23,6 +23,7 @@ E_NOMEM = -6
 OP_EMBED = 0
 REF_COPY, REF_EMBED_MIX, REF_EXTRACT_MIX = 0, 1, 2
 OP_EXTRACT = 1
+OP_MIXED = 2
 
 ERROR_NAMES = {
     OK: "LSB_OK", E_ARG: "LSB_E_ARG", E_CAPACITY: "LSB_E_CAPACITY", E_HEADER: "LSB_E_HEADER",
@@ -92,9 +93,11 @@ SIGNATURES = {
     "lsb_sse": (_I, [_P, _P, _U64, _P, _P]),
     "lsb_video_embed_host": (_I, [_P, _P, _U64, _U64, _P, _U64, _I, _P, _U32, _P, _P, _P]),
     "lsb_verify": (_I, [_P, _P, _U64, _P, _U32, _I, _P, _P]),
-    "lsb_plan_create": (_I, [ctypes.POINTER(_P), _I]),
-    "lsb_plan_set_jobs": (_I, [_P, ctypes.POINTER(Job), _I]),
+    "lsb_plan_create": (_I, [ctypes.POINTER(_P), ctypes.POINTER(Job), _I, _I]),
+    "lsb_plan_update": (_I, [_P, ctypes.POINTER(Job), _I]),
     "lsb_plan_run": (_I, [_P, _P, _P, _P, _P, _P, _P]),
+    "lsb_embed_batch": (_I, [_P, _P, _P, _P, _P, _P]),
+    "lsb_extract_batch": (_I, [_P, _P, _P, _P, _P, _P]),
     "lsb_plan_tiles": (_I64, [_P]),
     "lsb_plan_destroy": (None, [_P]),
     "lsb_tune_get": (_I, [_I, _I, _U64, ctypes.POINTER(LaunchCfg)]),

@@ -7,7 +7,7 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import OP_EMBED, OP_EXTRACT, Job, LaunchCfg, check, lib
+from ._lib import OP_EMBED, OP_EXTRACT, OP_MIXED, Job, LaunchCfg, check, lib
 
 ALIGN = 256
 
@@ -36,17 +36,43 @@ class Plan:
     """Owns an lsb_plan: a device job table, its pinned host mirror and the
     HIP graph {table upload, prologue, persistent kernel}."""
 
-    def __init__(self, max_jobs: int):
+    def __init__(self, max_jobs: int, op: int = OP_MIXED, jobs: np.ndarray | None = None):
+        """Room for ``max_jobs`` jobs; ``op`` = OP_EMBED / OP_EXTRACT makes
+        every job that kind, OP_MIXED keeps each job's op field.  ``jobs``,
+        if given, is installed at creation (lsb_plan_create)."""
         self._p = ctypes.c_void_p()
-        check(lib().lsb_plan_create(ctypes.byref(self._p), int(max_jobs)))
+        ptr = None
+        if jobs is not None:
+            jobs = np.ascontiguousarray(jobs, dtype=JOB_DTYPE)
+            if jobs.size != max_jobs:
+                raise ValueError("jobs given at creation must number max_jobs")
+            ptr = jobs.ctypes.data_as(ctypes.POINTER(Job))
+        check(lib().lsb_plan_create(ctypes.byref(self._p), ptr, int(max_jobs), int(op)))
         self.max_jobs = int(max_jobs)
-        self.n_jobs = 0
+        self.n_jobs = int(max_jobs) if jobs is not None else 0
 
     def set_jobs(self, jobs: np.ndarray) -> None:
+        """Replace the job list (lsb_plan_update)."""
         jobs = np.ascontiguousarray(jobs, dtype=JOB_DTYPE)
         ptr = jobs.ctypes.data_as(ctypes.POINTER(Job)) if jobs.size else None
-        check(lib().lsb_plan_set_jobs(self._p, ptr, int(jobs.size)))
+        check(lib().lsb_plan_update(self._p, ptr, int(jobs.size)))
         self.n_jobs = int(jobs.size)
+
+    update = set_jobs
+
+    def embed_batch(self, cover_arena, stego_arena, msg_arena, status_dev, stream=None) -> None:
+        """lsb_embed_batch: every job of the plan must be an embed."""
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        check(lib().lsb_embed_batch(self._p, _ptr(cover_arena), _ptr(stego_arena), _ptr(msg_arena),
+                                    _ptr(status_dev), ctypes.c_void_p(stream.cuda_stream)))
+
+    def extract_batch(self, stego_arena, msg_arena, len_dev, status_dev, stream=None) -> None:
+        """lsb_extract_batch: every job of the plan must be an extract."""
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        check(lib().lsb_extract_batch(self._p, _ptr(stego_arena), _ptr(msg_arena), _ptr(len_dev),
+                                      _ptr(status_dev), ctypes.c_void_p(stream.cuda_stream)))
 
     @property
     def tiles(self) -> int:

@@ -189,7 +189,9 @@ struct lsb_plan {
     int device = -1;
     int max_jobs = 0;
     int n_jobs = 0;
+    int op_mode = LSB_OP_MIXED;  // LSB_OP_EMBED / LSB_OP_EXTRACT: every job of that kind
     bool has_extract = false;
+    bool has_embed = false;
     uint64_t total_tiles = 0;
     size_t table_bytes = 0;  // bytes of header + (max_jobs + 1) records
     size_t used_bytes = 0;   // bytes the next upload copies
@@ -286,17 +288,20 @@ static int prepare_graph(lsb_plan *p) {
 
 extern "C" {
 
-int lsb_plan_create(lsb_plan **out, int max_jobs) {
+int lsb_plan_create(lsb_plan **out, const lsb_job *jobs, int n_jobs, int op) {
     clear_error();
     if (!out) return fail(LSB_E_ARG, "lsb_plan_create: null plan pointer");
     *out = nullptr;
-    if (max_jobs < 1 || max_jobs > (1 << 24)) return fail(LSB_E_ARG, "lsb_plan_create: max_jobs=%d", max_jobs);
+    if (n_jobs < 1 || n_jobs > (1 << 24)) return fail(LSB_E_ARG, "lsb_plan_create: n_jobs=%d", n_jobs);
+    if (op != LSB_OP_EMBED && op != LSB_OP_EXTRACT && op != LSB_OP_MIXED)
+        return fail(LSB_E_ARG, "lsb_plan_create: op=%d", op);
     lsb_plan *p = new (std::nothrow) lsb_plan();
     if (!p) return fail(LSB_E_NOMEM, "lsb_plan_create: out of host memory");
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) return delete p, hip_fail(e, "hipGetDevice");
-    p->max_jobs = max_jobs;
-    p->table_bytes = sizeof(PlanHeader) + sizeof(DevJob) * ((size_t)max_jobs + 1);
+    p->max_jobs = n_jobs;
+    p->op_mode = op;
+    p->table_bytes = sizeof(PlanHeader) + sizeof(DevJob) * ((size_t)n_jobs + 1);
     e = hipHostMalloc((void **)&p->host, p->table_bytes, hipHostMallocDefault);
     if (e != hipSuccess) return delete p, fail(LSB_E_NOMEM, "lsb_plan_create: hipHostMalloc failed");
     e = hipMalloc((void **)&p->dev, p->table_bytes);
@@ -305,16 +310,23 @@ int lsb_plan_create(lsb_plan **out, int max_jobs) {
     if (e != hipSuccess) return hipFree(p->dev), hipHostFree(p->host), delete p, hip_fail(e, "hipEventCreate");
     memset(p->host, 0, p->table_bytes);
     p->used_bytes = sizeof(PlanHeader) + sizeof(DevJob);
+    if (jobs) {
+        const int rc = lsb_plan_update(p, jobs, n_jobs);
+        if (rc != LSB_OK) {
+            lsb_plan_destroy(p);
+            return rc;
+        }
+    }
     *out = p;
     return LSB_OK;
 }
 
-int lsb_plan_set_jobs(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
+int lsb_plan_update(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
     clear_error();
-    if (!p) return fail(LSB_E_ARG, "lsb_plan_set_jobs: null plan");
+    if (!p) return fail(LSB_E_ARG, "lsb_plan_update: null plan");
     if (n_jobs < 0 || n_jobs > p->max_jobs)
-        return fail(LSB_E_ARG, "lsb_plan_set_jobs: n_jobs=%d outside 0..%d", n_jobs, p->max_jobs);
-    if (n_jobs && !jobs) return fail(LSB_E_ARG, "lsb_plan_set_jobs: null job list");
+        return fail(LSB_E_ARG, "lsb_plan_update: n_jobs=%d outside 0..%d", n_jobs, p->max_jobs);
+    if (n_jobs && !jobs) return fail(LSB_E_ARG, "lsb_plan_update: null job list");
     int64_t tv;
     {
         std::lock_guard<std::mutex> g(g_batch_mu);
@@ -324,7 +336,8 @@ int lsb_plan_set_jobs(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
     for (int i = 0; i < n_jobs; ++i) {
         const lsb_job &J = jobs[i];
         if (J.k < 1 || J.k > 8) return fail(LSB_E_ARG, "job %d: k=%d outside 1..8", i, (int)J.k);
-        if (J.op != LSB_OP_EMBED && J.op != LSB_OP_EXTRACT) return fail(LSB_E_ARG, "job %d: bad op %d", i, (int)J.op);
+        if (p->op_mode == LSB_OP_MIXED && J.op != LSB_OP_EMBED && J.op != LSB_OP_EXTRACT)
+            return fail(LSB_E_ARG, "job %d: bad op %d", i, (int)J.op);
         if ((J.cover_off | J.stego_off | J.msg_off) & 255)
             return fail(LSB_E_ARG, "job %d: arena offsets must be multiples of 256", i);
         if (J.n > (1ull << 48)) return fail(LSB_E_ARG, "job %d: n out of range", i);
@@ -338,9 +351,10 @@ int lsb_plan_set_jobs(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
     PlanHeader *h = (PlanHeader *)p->host;
     DevJob *d = (DevJob *)(p->host + sizeof(PlanHeader));
     uint64_t tiles = 0;
-    bool has_extract = false;
+    bool has_extract = false, has_embed = false;
     for (int i = 0; i < n_jobs; ++i) {
         const lsb_job &J = jobs[i];
+        const uint8_t op = p->op_mode == LSB_OP_MIXED ? J.op : (uint8_t)p->op_mode;
         DevJob &D = d[i];
         memset(&D, 0, sizeof D);
         D.cover_off = J.cover_off;
@@ -350,11 +364,12 @@ int lsb_plan_set_jobs(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
         D.msg_cap = J.msg_cap;
         D.len = J.len;
         D.k = J.k;
-        D.op = J.op;
+        D.op = op;
         D.tile_begin = tiles;
         D.status = LSB_OK;
         uint64_t vectors = ceil_div(J.n, 16);
-        if (J.op == LSB_OP_EMBED) {
+        if (op == LSB_OP_EMBED) {
+            has_embed = true;
             const uint64_t room = room_bytes(J.n, J.k);
             if (room < 4 || (uint64_t)J.len > room - 4) {
                 D.status = LSB_E_CAPACITY;
@@ -381,6 +396,7 @@ int lsb_plan_set_jobs(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
     p->n_jobs = n_jobs;
     p->total_tiles = tiles;
     p->has_extract = has_extract;
+    p->has_embed = has_embed;
     p->tile_vectors = tv;
     p->used_bytes = sizeof(PlanHeader) + sizeof(DevJob) * ((size_t)n_jobs + 1);
     return LSB_OK;
@@ -408,7 +424,7 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
         cfg = g_batch_cfg;
         tv = g_tile_vectors;
     }
-    if (tv != p->tile_vectors) return fail(LSB_E_ARG, "lsb_plan_run: tile size changed since lsb_plan_set_jobs");
+    if (tv != p->tile_vectors) return fail(LSB_E_ARG, "lsb_plan_run: tile size changed since lsb_plan_update");
     const bool rebuild = p->exec && (cfg.block != p->cfg.block || cfg.unroll != p->cfg.unroll ||
                                      cfg.nontemporal != p->cfg.nontemporal);
     if (rebuild) destroy_graph(p);
@@ -433,6 +449,26 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord(plan)");
     p->ran = true;
     return LSB_OK;
+}
+
+int lsb_embed_batch(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, const uint8_t *msg_arena,
+                    int32_t *status_dev, void *stream) {
+    clear_error();
+    if (!p) return fail(LSB_E_ARG, "lsb_embed_batch: null plan");
+    if (p->has_extract) return fail(LSB_E_ARG, "lsb_embed_batch: the plan holds extract jobs");
+    if (p->n_jobs && !cover_arena) return fail(LSB_E_ARG, "lsb_embed_batch: null cover arena");
+    // embed jobs only read the message arena
+    return lsb_plan_run(p, cover_arena, stego_arena, const_cast<uint8_t *>(msg_arena), nullptr, status_dev, stream);
+}
+
+int lsb_extract_batch(lsb_plan *p, const uint8_t *stego_arena, uint8_t *msg_arena, uint32_t *len_dev,
+                      int32_t *status_dev, void *stream) {
+    clear_error();
+    if (!p) return fail(LSB_E_ARG, "lsb_extract_batch: null plan");
+    if (p->has_embed) return fail(LSB_E_ARG, "lsb_extract_batch: the plan holds embed jobs");
+    if (p->n_jobs && !len_dev) return fail(LSB_E_ARG, "lsb_extract_batch: null len_dev");
+    // extract jobs only read the stego arena
+    return lsb_plan_run(p, nullptr, const_cast<uint8_t *>(stego_arena), msg_arena, len_dev, status_dev, stream);
 }
 
 void lsb_plan_destroy(lsb_plan *p) {

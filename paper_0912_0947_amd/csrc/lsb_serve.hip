@@ -132,7 +132,7 @@ class HipExecutor : public Executor {
             if (e == hipSuccess) e = hipHostMalloc((void **)&s.len_host, sizeof(uint32_t) * 2 * B_, hipHostMallocDefault);
             if (e != hipSuccess) return hip_fail(e, "lsb_serve: slot setup");
             for (int op = 0; op < 2; ++op) {
-                const int rc = lsb_plan_create(&s.plan[op], B_);
+                const int rc = lsb_plan_create(&s.plan[op], nullptr, B_, op);
                 if (rc != LSB_OK) return rc;
             }
         }
@@ -144,7 +144,7 @@ class HipExecutor : public Executor {
         const int cnt[2] = {ne, nx};
         for (int op = 0; op < 2; ++op) {
             if (!cnt[op]) continue;
-            int rc = lsb_plan_set_jobs(s.plan[op], jobs[op], cnt[op]);
+            int rc = lsb_plan_update(s.plan[op], jobs[op], cnt[op]);
             if (rc != LSB_OK) return rc;
             int32_t *st = s.status_dev + op * B_;
             uint32_t *ln = s.len_dev + op * B_;

@@ -29,7 +29,7 @@ def lib():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ["lsb_capacity", "lsb_embed", "lsb_extract", "lsb_extract_sync", "lsb_embed_raw",
-                 "lsb_extract_raw", "lsb_plan_create", "lsb_plan_set_jobs", "lsb_plan_run",
+                 "lsb_extract_raw", "lsb_plan_create", "lsb_plan_update", "lsb_plan_run", "lsb_embed_batch", "lsb_extract_batch",
                  "lsb_plan_destroy", "lsb_last_error", "lsb_autotune", "lsb_tune_set", "lsb_tune_get"]:
         assert must in names
 

@@ -189,6 +189,50 @@ def test_plan_errors():
         plan.close()
 
 
+def test_plan_kinds_and_named_calls():
+    """A plan created for one kind treats every job as that kind whatever its
+    op field says; lsb_embed_batch / lsb_extract_batch refuse plans holding
+    the other kind; results equal the mixed plan's."""
+    wl = BatchWorkload(24, oracle.capacity, seed=421, lo=64, hi=700)
+    cover, stego, msg, out = wl.allocate(DEV)
+    status = torch.full((wl.count,), 99, dtype=torch.int32, device=DEV)
+    lens = torch.zeros(wl.count, dtype=torch.int32, device=DEV)
+    jobs_e = wl.jobs(OP_EMBED)
+    wrong = jobs_e.copy()
+    wrong["op"] = OP_EXTRACT  # ignored by an embed-only plan
+    pe = batch.Plan(wl.count, OP_EMBED, wrong)
+    px = batch.Plan(wl.count, OP_EXTRACT)
+    mixed = batch.Plan(wl.count)
+    try:
+        stego.zero_()  # the arena's alignment gaps are never written: start both runs from zeros
+        pe.embed_batch(cover, stego, msg, status)
+        torch.cuda.synchronize()
+        assert bool((status == OK).all())
+        ref = stego.clone()
+        mixed.set_jobs(jobs_e)
+        stego.zero_()
+        mixed.run(cover, stego, msg, lens, status)
+        torch.cuda.synchronize()
+        assert torch.equal(stego, ref)
+        px.update(wl.jobs(OP_EXTRACT))
+        px.extract_batch(stego, out, lens, status)
+        torch.cuda.synchronize()
+        assert bool((status == OK).all())
+        for i in range(wl.count):
+            o, ln = int(wl.msg_off[i]), int(wl.len[i])
+            assert torch.equal(out[o:o + ln], msg[o:o + ln]), i
+        with pytest.raises(Exception):
+            px.embed_batch(cover, stego, msg, status)
+        with pytest.raises(Exception):
+            pe.extract_batch(stego, out, lens, status)
+        with pytest.raises(Exception):
+            batch.Plan(4, 7)  # unknown op
+    finally:
+        pe.close()
+        px.close()
+        mixed.close()
+
+
 def test_config4_full_scale():
     """4096 uneven covers (W, H ~ U{64..4096}, 1 or 3 channels, k in {1, 2},
     message 10-100 % of capacity; about 35 GB of covers): one batched embed and
@@ -199,20 +243,21 @@ def test_config4_full_scale():
     cover, stego, msg, out = wl.allocate(DEV)
     status = torch.full((wl.count,), 99, dtype=torch.int32, device=DEV)
     lens = torch.zeros(wl.count, dtype=torch.int32, device=DEV)
-    plan = batch.Plan(wl.count)
+    # the boundary's named calls: a plan per kind, created with its jobs
+    pe = batch.Plan(wl.count, OP_EMBED, wl.jobs(OP_EMBED))
+    px = batch.Plan(wl.count, OP_EXTRACT, wl.jobs(OP_EXTRACT))
     try:
-        plan.set_jobs(wl.jobs(OP_EMBED))
-        plan.run(cover, stego, msg, lens, status)
+        pe.embed_batch(cover, stego, msg, status)
         torch.cuda.synchronize()
         assert bool((status == OK).all())
-        plan.set_jobs(wl.jobs(OP_EXTRACT))
         status.fill_(99)
-        plan.run(None, stego, out, lens, status)
+        px.extract_batch(stego, out, lens, status)
         torch.cuda.synchronize()
         assert bool((status == OK).all())
         assert np.array_equal(lens.cpu().numpy().astype(np.int64), wl.len)
     finally:
-        plan.close()
+        pe.close()
+        px.close()
     scratch = torch.empty(int(wl.n.max()), dtype=torch.uint8, device=DEV)
     for i in range(wl.count):
         c0, n, m0, ln, k = int(wl.cover_off[i]), int(wl.n[i]), int(wl.msg_off[i]), int(wl.len[i]), int(wl.k[i])

@@ -69,8 +69,9 @@ def test_row_kernel_shapes(seed):
 
 
 def test_wide_rows_fall_back():
-    """A row whose data chunk exceeds the row kernel's staging limit takes the
-    per-vector kernel (w = 262,144 pixels: 65,536 data bytes per row)."""
+    """A row whose data chunk exceeds the row kernels' LDS limit takes the
+    per-vector embed and per-byte extract (w = 262,144 pixels: 65,536 data
+    bytes per row)."""
     h, w, c = 3, 262144, 1
     cap = oracle.paper_capacity(h, w)
     ln = cap - 1000
@@ -79,6 +80,7 @@ def test_wide_rows_fall_back():
     rc, want = oracle.paper_embed(cover, h, w, c, 0, data)
     st = api.paper_embed(to_dev(cover), h, w, c, 0, to_dev(data))
     assert_bytes_equal(to_host(st), want, "wide rows")
+    assert_bytes_equal(to_host(api.paper_extract(st, h, w, c, 0, ln)), data, "wide rows extract")
 
 
 def test_session_shape():

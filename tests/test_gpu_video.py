@@ -32,3 +32,32 @@ def test_pipelined_frames_equal_device_embed(k, slots):
     assert torch.equal(out, want_dev.cpu()), "pipelined frames differ from the device embed"
     rc, want = oracle.embed_raw(clip.numpy(), 0, stream, stream_bits, k)
     assert_bytes_equal(out.numpy(), want, "pipelined frames vs oracle k=%d" % k)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_per_frame_launches_in_a_graph(k):
+    """Per-frame raw embeds (no allocation, no synchronisation, no memset
+    inside) captured once in a HIP graph: every replay, with eager work and
+    synchronisation between replays, matches the oracle."""
+    frames, h, w = 16, 40, 64
+    fb = h * w * 3
+    clip_np = inputs.video_frames(frames, h, w, device="cpu").view(-1).numpy().copy()
+    stream_bits = clip_np.size * k * 2 // 3 + 5
+    stream = inputs.random_bytes((stream_bits + 7) // 8, 1811, k)
+    rc, want = oracle.embed_raw(clip_np, 0, stream, stream_bits, k)
+    assert rc == 0
+    clip = torch.from_numpy(clip_np).to(DEV)
+    sd = torch.from_numpy(stream).to(DEV)
+    out = torch.empty_like(clip)
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=side):
+        for f in range(frames):
+            api.embed_raw(clip[f * fb:(f + 1) * fb], f * fb, sd, stream_bits, k, out=out[f * fb:(f + 1) * fb])
+    for rep in range(3):
+        out.fill_(rep)  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert_bytes_equal(to_host(out), want, "graph replay %d, k=%d" % (rep, k))
