@@ -160,18 +160,22 @@ int lsb_sse(const uint8_t *a, const uint8_t *b, uint64_t n, uint64_t *sse_dev,
 /* ------------------------------------------------------------------------
  * Host-streamed video (the paper's copy-in / launch / copy-out flow of
  * Sections III and V, pipelined): `frames` frames of `frame_bytes` bytes in
- * pinned host memory are copied to a ring of `ring_slots` device slots
- * (dev_ring holds ring_slots * frame_bytes bytes), embedded in place as raw
- * slices t0 = f * frame_bytes of one logical stream (stream_dev, a device
- * buffer of stream_bits bits), and copied back to host_stego, on three
- * distinct streams (copy in, compute, copy out) ordered by events.  Returns
- * after enqueueing; host_stego is complete once s_out has drained.
- */
+ * pinned host memory are embedded in place as raw slices t0 = f *
+ * frame_bytes of one logical stream (stream_dev, a device buffer of
+ * stream_bits bits) and copied back to host_stego.  Frame f goes to stream
+ * streams[f % n_streams] (1 <= n_streams <= 16, distinct streams), which
+ * copies it into ring slot f % ring_slots (dev_ring holds ring_slots *
+ * frame_bytes bytes), embeds it and copies it back, in stream order.
+ * ring_slots must be a positive multiple of n_streams, so that a slot is
+ * only reused by a later frame of the same stream: no events or cross-stream
+ * waits are needed, and the copies of different streams run in both PCIe
+ * directions at once.  Returns after enqueueing; host_stego is complete once
+ * every stream has drained.  Errors: LSB_E_ARG. */
 int lsb_video_embed_host(const uint8_t *host_frames, uint8_t *host_stego,
                          uint64_t frame_bytes, uint64_t frames,
-                         const uint8_t *stream_dev, uint64_t stream_bits,
-                         int k, uint8_t *dev_ring, uint32_t ring_slots,
-                         void *s_in, void *s_compute, void *s_out);
+                         const uint8_t *stream_dev, uint64_t stream_bits, int k,
+                         uint8_t *dev_ring, uint32_t ring_slots,
+                         void *const *streams, int n_streams);
 
 /* ------------------------------------------------------------------------
  * Verification in one launch: *mismatches_dev (overwritten) receives the

@@ -179,23 +179,24 @@ def psnr(sse_value: int, count: int) -> float:
 
 def video_embed_host(host_frames: torch.Tensor, host_stego: torch.Tensor, frame_bytes: int,
                      stream_bytes: torch.Tensor, stream_bits: int, k: int, ring: torch.Tensor, streams):
-    """Pipeline frames from pinned host memory through the device ring:
-    copy in, embed in place (raw slice t0 = f * frame_bytes), copy out, on the
-    three streams ``streams`` = (copy in, compute, copy out).  Returns after
-    enqueueing; synchronize the third stream before reading host_stego."""
+    """Pipeline frames from pinned host memory through the device ring: frame
+    f goes to ``streams[f % len(streams)]``, which copies it in, embeds it in
+    place (raw slice t0 = f * frame_bytes) and copies it out.  The ring's slot
+    count is rounded down to a multiple of the stream count.  Returns after
+    enqueueing; synchronize every stream before reading host_stego."""
     for t, name in ((host_frames, "host_frames"), (host_stego, "host_stego")):
         if t.is_cuda or not t.is_pinned() or t.dtype != torch.uint8 or not t.is_contiguous():
             raise TypeError("%s must be a contiguous pinned uint8 host tensor" % name)
     if host_frames.numel() % frame_bytes or host_stego.numel() != host_frames.numel():
         raise ValueError("host buffers must hold whole frames, stego as many bytes as frames")
-    slots = ring.numel() // frame_bytes
+    streams = list(streams)
+    slots = ring.numel() // frame_bytes // len(streams) * len(streams)
     if slots < 1:
-        raise ValueError("ring must hold at least one frame")
-    s_in, s_c, s_out = streams
+        raise ValueError("ring must hold at least one frame per stream")
+    arr = (ctypes.c_void_p * len(streams))(*[s.cuda_stream for s in streams])
     check(lib().lsb_video_embed_host(ctypes.c_void_p(host_frames.data_ptr()), ctypes.c_void_p(host_stego.data_ptr()),
                                      frame_bytes, host_frames.numel() // frame_bytes, _u8(stream_bytes, "stream_bytes"),
-                                     stream_bits, k, _u8(ring, "ring"), slots, ctypes.c_void_p(s_in.cuda_stream),
-                                     ctypes.c_void_p(s_c.cuda_stream), ctypes.c_void_p(s_out.cuda_stream)))
+                                     stream_bits, k, _u8(ring, "ring"), slots, arr, len(streams)))
 
 
 def verify(cover: torch.Tensor, stego: torch.Tensor, msg: torch.Tensor, k: int,

@@ -67,11 +67,19 @@ def load(handle=None, path: str = TABLE) -> bool:
 
 
 def tune_rotating(op: int, k: int, n: int, sets, reps: int = 9):
-    """Steady-state choice for one (op, k, n): every candidate launch shape is
-    launched ``reps`` times over the buffer sets in turn, each launch timed by
-    events bound to the kernel itself; the lowest median wins and is installed
-    for n's bucket.  ``sets`` holds (cover, stego, msg, out, len_status) per
-    set; every stego already carries a full-capacity stream."""
+    """Steady-state choice for one (op, k, n).  Each repetition launches every
+    candidate shape once, in turn, over the buffer sets (round-robin, so slow
+    drift of the device during the sweep affects all candidates alike); each
+    launch is timed by events bound to the kernel itself.  The lowest median
+    wins and is installed for n's bucket.  Returns (cfg, median us, the next
+    best three as (cfg, us)).  ``sets`` holds (cover, stego, msg, out,
+    len_status) per set; every stego already carries a full-capacity stream.
+
+    Buffers beyond the last-level cache get streaming (non-temporal) shapes
+    only: cached stores cannot be reused at these sizes, they only leave dirty
+    lines that the next kernel has to write back (a k = 4 extract with cached
+    stores measured faster alone but slowed itself and the embed after it by
+    about 6 % in the embed/extract sequence)."""
     import statistics
 
     import torch
@@ -82,42 +90,30 @@ def tune_rotating(op: int, k: int, n: int, sets, reps: int = 9):
     L = lib()
     cap = api.capacity(n, k)
     packs = (0, 1) if (op == api.OP_EXTRACT and k == 1) else (0,)
-    best = None
+    cands = [{"block": b, "unroll": u, "blocks_per_cu": c, "nontemporal": 1, "pack": pk}
+             for pk in packs for b in BLOCKS for u in UNROLLS for c in CAPS]
+    times = [[] for _ in cands]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cands]
     it = 0
-    # Buffers beyond the last-level cache get streaming (non-temporal) loads
-    # and stores only: cached stores cannot be reused at these sizes, they only
-    # leave dirty lines that the next kernel has to write back (a k = 4
-    # extract with cached stores measured faster alone but slowed itself and
-    # the embed after it by about 6 % in the embed/extract sequence).
-    for pack in packs:
-        for nt in (1,):
-            for block in BLOCKS:
-                for unroll in UNROLLS:
-                    for capb in CAPS:
-                        api.tune_set(op, k, bucket(n), block, unroll, capb, nt, pack)
-                        ms = []
-                        for r in range(reps + 1):
-                            cover, stego, msg, out, ls = sets[it % len(sets)]
-                            it += 1
-                            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                            e0.record()
-                            e1.record()
-                            torch.cuda.synchronize()
-                            L.lsb_time_next_launch(e0, e1)
-                            if op == api.OP_EMBED:
-                                api.embed(cover[:n], msg[:cap], k, out=stego[:n])
-                            else:
-                                api.extract(stego[:n], k, out=out[:cap], len_status=ls)
-                            torch.cuda.synchronize()
-                            if r:
-                                ms.append(e0.elapsed_time(e1))
-                        us = statistics.median(ms) * 1e3
-                        if best is None or us < best[1]:
-                            best = ({"block": block, "unroll": unroll, "blocks_per_cu": capb, "nontemporal": nt,
-                                     "pack": pack}, us)
-    c = best[0]
-    api.tune_set(op, k, bucket(n), c["block"], c["unroll"], c["blocks_per_cu"], c["nontemporal"], c["pack"])
-    return best
+    for r in range(reps + 1):
+        for ci, c in enumerate(cands):
+            api.tune_set(op, k, bucket(n), c["block"], c["unroll"], c["blocks_per_cu"], c["nontemporal"], c["pack"])
+            cover, stego, msg, out, ls = sets[it % len(sets)]
+            it += 1
+            e0, e1 = ev[ci]
+            L.lsb_time_next_launch(e0, e1)
+            if op == api.OP_EMBED:
+                api.embed(cover[:n], msg[:cap], k, out=stego[:n])
+            else:
+                api.extract(stego[:n], k, out=out[:cap], len_status=ls)
+            torch.cuda.synchronize()
+            if r:  # repetition 0 warms every shape up
+                times[ci].append(e0.elapsed_time(e1))
+    med = sorted((statistics.median(t) * 1e3, ci) for ci, t in enumerate(times))
+    best = cands[med[0][1]]
+    api.tune_set(op, k, bucket(n), best["block"], best["unroll"], best["blocks_per_cu"], best["nontemporal"],
+                 best["pack"])
+    return best, med[0][0], [(cands[ci], round(us, 2)) for us, ci in med[1:4]]
 
 
 def tune_plain(reps: int = 5, sizes=SIZES, ks=KS, log=print):
@@ -162,10 +158,10 @@ def tune_plain(reps: int = 5, sizes=SIZES, ks=KS, log=print):
                 for cover, stego, msg, _, _ in sets:  # stegos carry full-capacity streams
                     api.embed(cover[:n], msg[:cap], k, out=stego[:n])
                 for op in (api.OP_EMBED, api.OP_EXTRACT):
-                    cfg, us = tune_rotating(op, k, n, sets, reps=max(reps, 9))
+                    cfg, us, runners = tune_rotating(op, k, n, sets, reps=max(reps, 9))
                     entries.append({"op": op, "k": k, "bucket": bucket(n), "n": n, "cfg": cfg, "us": round(us, 2),
-                                    "method": "rotating"})
-                    log("op=%d k=%d n=%d -> %s %.1f us (rotating)" % (op, k, n, cfg, us))
+                                    "method": "rotating", "runners_up": runners})
+                    log("op=%d k=%d n=%d -> %s %.1f us (rotating; next %s)" % (op, k, n, cfg, us, runners))
                 # the extracts above must have returned every message
                 for cover, stego, msg, out, ls in sets:
                     st = ls.cpu().tolist()

@@ -12,9 +12,9 @@ from gpu_helpers import DEV, assert_bytes_equal, to_host
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("k,slots", [(1, 3), (2, 1), (3, 4)])
-def test_pipelined_frames_equal_device_embed(k, slots):
-    frames, h, w = 24, 48, 80
+@pytest.mark.parametrize("k,n_streams,slots", [(1, 2, 2), (2, 1, 1), (3, 2, 4), (1, 3, 6), (2, 4, 4)])
+def test_pipelined_frames_equal_device_embed(k, n_streams, slots):
+    frames, h, w = 25, 48, 80
     fb = h * w * 3
     clip = inputs.video_frames(frames, h, w, device="cpu").view(-1).contiguous()
     stream_bits = clip.numel() * k * 2 // 3 + 7
@@ -22,11 +22,12 @@ def test_pipelined_frames_equal_device_embed(k, slots):
     host = clip.pin_memory()
     out = torch.empty_like(host).pin_memory()
     ring = torch.empty(slots * fb, dtype=torch.uint8, device=DEV)
-    streams = [torch.cuda.Stream() for _ in range(3)]
+    streams = [torch.cuda.Stream() for _ in range(n_streams)]
     sd = torch.from_numpy(stream).to(DEV)
     torch.cuda.synchronize()
     api.video_embed_host(host, out, fb, sd, stream_bits, k, ring, streams)
-    streams[2].synchronize()
+    for st in streams:
+        st.synchronize()
     torch.cuda.synchronize()
     want_dev = api.embed_raw(clip.to(DEV), 0, sd, stream_bits, k)
     assert torch.equal(out, want_dev.cpu()), "pipelined frames differ from the device embed"
@@ -61,3 +62,21 @@ def test_per_frame_launches_in_a_graph(k):
         g.replay()
         torch.cuda.synchronize()
         assert_bytes_equal(to_host(out), want, "graph replay %d, k=%d" % (rep, k))
+
+
+def test_pipeline_argument_errors():
+    fb = 64 * 64 * 3
+    host = torch.zeros(4 * fb, dtype=torch.uint8).pin_memory()
+    out = torch.zeros(4 * fb, dtype=torch.uint8).pin_memory()
+    sd = torch.zeros(16, dtype=torch.uint8, device=DEV)
+    s = torch.cuda.Stream()
+    ring = torch.empty(2 * fb, dtype=torch.uint8, device=DEV)
+    with pytest.raises(Exception):  # the same stream twice
+        api.video_embed_host(host, out, fb, sd, 100, 1, ring, [s, s])
+    from paper_0912_0947_amd._lib import lib
+    import ctypes
+    arr = (ctypes.c_void_p * 2)(torch.cuda.Stream().cuda_stream, torch.cuda.Stream().cuda_stream)
+    # 3 slots are not a multiple of 2 streams
+    rc = lib().lsb_video_embed_host(ctypes.c_void_p(host.data_ptr()), ctypes.c_void_p(out.data_ptr()), fb, 4,
+                                    ctypes.c_void_p(sd.data_ptr()), 100, 1, ctypes.c_void_p(ring.data_ptr()), 3, arr, 2)
+    assert rc != 0
