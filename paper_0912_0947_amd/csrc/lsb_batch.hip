@@ -133,9 +133,13 @@ __device__ __forceinline__ void run_tile(const DevJob &J, uint64_t v_begin, uint
 
 // Persistent kernel.  Every wave of a block works on the block's tile; the
 // job of a tile is found by a forward search over the tile prefix that 64
-// lanes do in one step (jobs only move forward as the tile id grows).
+// lanes do in one step (jobs only move forward as the tile id grows).  All
+// sixteen (op, k) walkers are inlined behind one switch, which on its own
+// needs about 90 VGPRs (5 waves per SIMD); the launch bound asks for 8 waves
+// per SIMD at one vector per lane (41 VGPRs) and 6 at two (75 VGPRs), with no
+// spills.
 template <int UNR, bool NT>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(1024, UNR == 1 ? 8 : (UNR == 2 ? 6 : 4))
     lsb_batch_kernel(const PlanHeader *hdr, const DevJob *jobs, const uint8_t *cover_arena, uint8_t *stego_arena,
                      uint8_t *msg_arena, const uint32_t *len_dev, const int32_t *status_dev) {
     const uint32_t lane = threadIdx.x & 63u;

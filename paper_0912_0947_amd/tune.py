@@ -94,6 +94,10 @@ def tune_rotating(op: int, k: int, n: int, sets, reps: int = 9):
              for pk in packs for b in BLOCKS for u in UNROLLS for c in CAPS]
     times = [[] for _ in cands]
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cands]
+    for e0, e1 in ev:  # create the HIP events (torch records lazily); the library re-records them
+        e0.record()
+        e1.record()
+    torch.cuda.synchronize()
     it = 0
     for r in range(reps + 1):
         for ci, c in enumerate(cands):
@@ -114,6 +118,93 @@ def tune_rotating(op: int, k: int, n: int, sets, reps: int = 9):
     api.tune_set(op, k, bucket(n), best["block"], best["unroll"], best["blocks_per_cu"], best["nontemporal"],
                  best["pack"])
     return best, med[0][0], [(cands[ci], round(us, 2)) for us, ci in med[1:4]]
+
+
+# The large-image workload: embed then extract at k = 1, 2, 4 on one 8192 x
+# 8192 x 3 cover, every launch on a buffer the previous ones did not touch.
+SEQUENCE_N = 201326592
+SEQUENCE = ((0, 1), (1, 1), (0, 2), (1, 2), (0, 4), (1, 4))
+
+
+def tune_sequence(n: int = SEQUENCE_N, seq=SEQUENCE, reps: int = 7, log=print):
+    """Choose the shapes of the launches of a workload sequence inside that
+    sequence.  For each member (op, k) in turn every streaming candidate shape
+    is installed for n's bucket and the whole sequence runs reps + 1 times
+    over three rotating buffer sets, the member's launch timed by events bound
+    to it; the lowest median wins before the next member is tuned.  Same-op
+    rotation ranks near-equal shapes by noise: in this sequence the preceding
+    kernels' traffic separates them (one shape that tied in rotation ran 10 %
+    slower here).  Returns table entries."""
+    import statistics
+
+    import torch
+
+    from . import api, inputs
+    from ._lib import lib
+
+    L = lib()
+    dev = torch.device("cuda:0")
+    ks = sorted({k for _, k in seq})
+    sets = 3
+    covers = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(sets)]
+    for i, c in enumerate(covers):
+        inputs.fill_uniform(c, 31 + i)
+    msgs = {k: torch.empty(api.capacity(n, k), dtype=torch.uint8, device=dev) for k in ks}
+    for k, m in msgs.items():
+        inputs.fill_uniform(m, 41 + k)
+    stegos = {k: [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(sets)] for k in ks}
+    outs = {k: [torch.empty(msgs[k].numel(), dtype=torch.uint8, device=dev) for _ in range(sets)] for k in ks}
+    ls = torch.zeros((len(ks), sets, 2), dtype=torch.int32, device=dev)
+    for k in ks:
+        for j in range(sets):
+            api.embed(covers[j], msgs[k], k, out=stegos[k][j])
+    torch.cuda.synchronize()
+    it = [0]
+
+    def run_sequence(target, events):
+        j = it[0] % sets
+        jx = (it[0] + 1) % sets
+        it[0] += 1
+        for op, k in seq:
+            if (op, k) == target:
+                L.lsb_time_next_launch(*events)
+            if op == api.OP_EMBED:
+                api.embed(covers[j], msgs[k], k, out=stegos[k][j])
+            else:
+                api.extract(stegos[k][jx], k, out=outs[k][jx], len_status=ls[ks.index(k), jx])
+
+    entries = []
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    for e in ev:
+        e.record()
+    torch.cuda.synchronize()
+    for op, k in seq:
+        best = None
+        for block in BLOCKS:
+            for unroll in UNROLLS:
+                for capb in CAPS:
+                    api.tune_set(op, k, bucket(n), block, unroll, capb, 1, 0)
+                    ms = []
+                    for r in range(reps + 1):
+                        run_sequence((op, k), ev)
+                        torch.cuda.synchronize()
+                        if r:
+                            ms.append(ev[0].elapsed_time(ev[1]))
+                    us = statistics.median(ms) * 1e3
+                    if best is None or us < best[1]:
+                        best = ({"block": block, "unroll": unroll, "blocks_per_cu": capb, "nontemporal": 1,
+                                 "pack": 0}, us)
+        c = best[0]
+        api.tune_set(op, k, bucket(n), c["block"], c["unroll"], c["blocks_per_cu"], 1, 0)
+        entries.append({"op": op, "k": k, "bucket": bucket(n), "n": n, "cfg": c, "us": round(best[1], 2),
+                        "method": "sequence"})
+        log("op=%d k=%d n=%d -> %s %.1f us (in the embed/extract sequence)" % (op, k, n, c, best[1]))
+    # every extract of the last pass returned its message
+    st = ls.cpu().numpy()
+    for ki, k in enumerate(ks):
+        for j in range(sets):
+            assert st[ki, j, 1] == 0 and st[ki, j, 0] == msgs[k].numel(), (k, j, st[ki, j])
+    return entries
 
 
 def tune_plain(reps: int = 5, sizes=SIZES, ks=KS, log=print):
@@ -185,11 +276,12 @@ def tune_batch(log=print, count: int = 4096):
     lens = torch.zeros(count, dtype=torch.int32, device=dev)
     best = None
     results = []
-    for tv in (4096, 16384, 65536):
-        for block in (256, 512):
-            for unroll in (2, 4):
+    # streaming stores only: the arenas (about 35 GB) are far beyond the cache
+    for tv in (4096, 16384):
+        for block in (256, 512, 1024):
+            for unroll in (1, 2, 4):
                 for bpc in (4, 8, 16):
-                    for nt in (0, 1):
+                    for nt in (1,):
                         batch.tune_set(block, unroll, bpc, nt, tv)
                         pe, px = batch.Plan(count), batch.Plan(count)
                         pe.set_jobs(wl.jobs(api.OP_EMBED))
@@ -222,8 +314,12 @@ def main():
     import torch
 
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    entries = tune_plain(args.reps, log=log)
+    # the large-image workload's launches are chosen inside its own sequence
+    seq = {(e["op"], e["k"], e["bucket"]): e for e in tune_sequence(log=log)}
+    entries = [seq.get((e["op"], e["k"], e["bucket"]), e) for e in entries]
     table = {"arch": "gfx950", "device": torch.cuda.get_device_name(0), "created": time.strftime("%Y-%m-%d %H:%M"),
-             "entries": tune_plain(args.reps, log=log)}
+             "entries": entries}
     if args.batch:
         table["batch"], table["batch_sweep"] = tune_batch(log=log)
     elif os.path.exists(args.out):

@@ -340,3 +340,38 @@ def test_ballot_packing_parity(block, unroll, nt):
                 assert_bytes_equal(to_host(out)[:ln], msg, "ballot n=%d len=%d off=%d" % (n, ln, off))
     finally:
         tune.load()
+
+
+@pytest.mark.parametrize("k", [1, 3, 8])
+def test_every_launch_shape(k):
+    """Every launch shape the tuner can install (block, vectors per lane, grid
+    cap, streaming loads/stores, and for the k = 1 extract the packing) gives
+    the oracle's stego and message on a ragged size with a partial last
+    field, so a re-tuned table cannot change results."""
+    from paper_0912_0947_amd import tune
+    n = 1000003
+    cover = inputs.random_bytes(n, 1961, k)
+    cap = oracle.capacity(n, k)
+    ln = cap - 5
+    msg = inputs.random_bytes(ln, 1962, k)
+    rc, want = oracle.embed(cover, msg, k)
+    assert rc == 0
+    cd, md, st = to_dev(cover), to_dev(msg), to_dev(want)
+    out = empty_dev(cap)
+    packs = (0, 1) if k == 1 else (0,)
+    try:
+        for block in tune.BLOCKS:
+            for unroll in tune.UNROLLS:
+                for capb in tune.CAPS:
+                    for nt in (0, 1):
+                        api.tune_set(api.OP_EMBED, k, -1, block, unroll, capb, nt)
+                        got = api.embed(cd, md, k)
+                        assert torch.equal(got, st), "embed k=%d shape %s" % (k, (block, unroll, capb, nt))
+                        for pack in packs:
+                            api.tune_set(api.OP_EXTRACT, k, -1, block, unroll, capb, nt, pack=pack)
+                            out.fill_(0)
+                            o, ls = api.extract(st, k, out=out)
+                            assert ls.cpu().tolist() == [ln, OK]
+                            assert torch.equal(o[:ln], md), "extract k=%d shape %s" % (k, (block, unroll, capb, nt, pack))
+    finally:
+        tune.load()
