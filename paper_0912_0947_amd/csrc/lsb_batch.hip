@@ -17,6 +17,7 @@
 
 #include <mutex>
 #include <new>
+#include <utility>
 
 #include "lsb_host.hpp"
 
@@ -88,7 +89,10 @@ __device__ __forceinline__ void extract_tile(const Span &s, uint64_t v_begin, ui
     if (v_begin < v_end) extract_walk<K, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane);
 }
 
-template <int UNR, bool NT>
+// CLS = 0: the tile's (op, k) is read from its job and dispatched by a switch
+// over all sixteen walkers; CLS = 1 + 8*op + (k - 1): every job of the plan
+// has that (op, k), and only its walker is compiled in.
+template <int UNR, bool NT, int CLS>
 __device__ __forceinline__ void run_tile(const DevJob &J, uint64_t v_begin, uint64_t tile_vectors,
                                          const uint8_t *cover_arena, uint8_t *stego_arena, uint8_t *msg_arena,
                                          uint32_t len, uint32_t wave, uint32_t n_waves, uint32_t lane) {
@@ -98,6 +102,23 @@ __device__ __forceinline__ void run_tile(const DevJob &J, uint64_t v_begin, uint
     s.k = J.k;
     s.hdr_len = 4;
     s.words = 1;  // offsets are multiples of 256: stream side is dword aligned
+    if constexpr (CLS > 0) {
+        constexpr int OP = (CLS - 1) / 8, K = (CLS - 1) % 8 + 1;
+        if constexpr (OP == LSB_OP_EMBED) {
+            s.src = cover_arena + J.cover_off;
+            s.dst = stego_arena + J.stego_off;
+            s.body = msg_arena + J.msg_off;
+            s.bits = 8 * (4 + (uint64_t)J.len);
+            s.hdr = J.len;
+            embed_tile<K, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane);
+        } else {
+            s.src = stego_arena + J.stego_off;
+            s.out = msg_arena + J.msg_off;
+            s.bits = 8 * (4 + (uint64_t)len);
+            extract_tile<K, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane);
+        }
+        return;
+    }
     if (J.op == LSB_OP_EMBED) {
         s.src = cover_arena + J.cover_off;
         s.dst = stego_arena + J.stego_off;
@@ -138,7 +159,7 @@ __device__ __forceinline__ void run_tile(const DevJob &J, uint64_t v_begin, uint
 // needs about 90 VGPRs (5 waves per SIMD); the launch bound asks for 8 waves
 // per SIMD at one vector per lane (41 VGPRs) and 6 at two (75 VGPRs), with no
 // spills.
-template <int UNR, bool NT>
+template <int UNR, bool NT, int CLS>
 __global__ void __launch_bounds__(1024, UNR == 1 ? 8 : (UNR == 2 ? 6 : 4))
     lsb_batch_kernel(const PlanHeader *hdr, const DevJob *jobs, const uint8_t *cover_arena, uint8_t *stego_arena,
                      uint8_t *msg_arena, const uint32_t *len_dev, const int32_t *status_dev) {
@@ -167,17 +188,26 @@ __global__ void __launch_bounds__(1024, UNR == 1 ? 8 : (UNR == 2 ? 6 : 4))
             len = len_dev[j];
         }
         const uint64_t v_begin = (tile - J.tile_begin) * tile_vectors;
-        run_tile<UNR, NT>(J, v_begin, tile_vectors, cover_arena, stego_arena, msg_arena, len, wave, n_waves, lane);
+        run_tile<UNR, NT, CLS>(J, v_begin, tile_vectors, cover_arena, stego_arena, msg_arena, len, wave, n_waves,
+                               lane);
     }
 }
 
 typedef void (*BatchFn)(const PlanHeader *, const DevJob *, const uint8_t *, uint8_t *, uint8_t *, const uint32_t *,
                         const int32_t *);
 
-static BatchFn batch_fn(int unroll, int nt) {
-    if (unroll == 1) return nt ? lsb_batch_kernel<1, true> : lsb_batch_kernel<1, false>;
-    if (unroll == 2) return nt ? lsb_batch_kernel<2, true> : lsb_batch_kernel<2, false>;
-    return nt ? lsb_batch_kernel<4, true> : lsb_batch_kernel<4, false>;
+template <int UNR, bool NT, int... C>
+static BatchFn batch_fn_of(int cls, std::integer_sequence<int, C...>) {
+    static const BatchFn table[] = {lsb_batch_kernel<UNR, NT, C>...};
+    return table[cls];
+}
+
+// Kernel for a launch shape and plan class (0 = mixed jobs).
+static BatchFn batch_fn(int unroll, int nt, int cls) {
+    using Classes = std::make_integer_sequence<int, 17>;
+    if (unroll == 1) return nt ? batch_fn_of<1, true>(cls, Classes{}) : batch_fn_of<1, false>(cls, Classes{});
+    if (unroll == 2) return nt ? batch_fn_of<2, true>(cls, Classes{}) : batch_fn_of<2, false>(cls, Classes{});
+    return nt ? batch_fn_of<4, true>(cls, Classes{}) : batch_fn_of<4, false>(cls, Classes{});
 }
 
 // Batched-kernel configuration (global, read at each run).
@@ -196,6 +226,7 @@ struct lsb_plan {
     int op_mode = LSB_OP_MIXED;  // LSB_OP_EMBED / LSB_OP_EXTRACT: every job of that kind
     bool has_extract = false;
     bool has_embed = false;
+    int cls = 0;  // 1 + 8*op + (k-1) when every job shares (op, k), else 0
     uint64_t total_tiles = 0;
     size_t table_bytes = 0;  // bytes of header + (max_jobs + 1) records
     size_t used_bytes = 0;   // bytes the next upload copies
@@ -401,6 +432,12 @@ int lsb_plan_update(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
     p->total_tiles = tiles;
     p->has_extract = has_extract;
     p->has_embed = has_embed;
+    p->cls = 0;
+    if (n_jobs > 0) {
+        bool same = true;
+        for (int i = 1; i < n_jobs && same; ++i) same = d[i].op == d[0].op && d[i].k == d[0].k;
+        if (same) p->cls = 1 + 8 * d[0].op + (d[0].k - 1);
+    }
     p->tile_vectors = tv;
     p->used_bytes = sizeof(PlanHeader) + sizeof(DevJob) * ((size_t)n_jobs + 1);
     return LSB_OK;
@@ -429,11 +466,13 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
         tv = g_tile_vectors;
     }
     if (tv != p->tile_vectors) return fail(LSB_E_ARG, "lsb_plan_run: tile size changed since lsb_plan_update");
-    const bool rebuild = p->exec && (cfg.block != p->cfg.block || cfg.unroll != p->cfg.unroll ||
-                                     cfg.nontemporal != p->cfg.nontemporal);
+    // a different kernel (shape or job class) cannot be swapped into the
+    // executable graph: rebuild it
+    const BatchFn fn = batch_fn(cfg.unroll, cfg.nontemporal, p->cls);
+    const bool rebuild = p->exec && (cfg.block != p->cfg.block || fn != p->fn);
     if (rebuild) destroy_graph(p);
     p->cfg = cfg;
-    p->fn = batch_fn(cfg.unroll, cfg.nontemporal);
+    p->fn = fn;
     const uint64_t cap_blocks = (uint64_t)(cfg.blocks_per_cu > 0 ? cfg.blocks_per_cu : 8) * (uint64_t)device_cus();
     p->main_grid = (unsigned)(p->total_tiles < cap_blocks ? (p->total_tiles ? p->total_tiles : 1) : cap_blocks);
     p->pro_grid = (unsigned)ceil_div((uint64_t)p->n_jobs, 4);  // 4 waves per block, one job per wave

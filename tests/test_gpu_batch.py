@@ -17,9 +17,10 @@ from gpu_helpers import DEV, assert_bytes_equal, to_host
 pytestmark = pytest.mark.gpu
 
 
-def _mixed_batch(count, seed):
+def _mixed_batch(count, seed, k_fixed=None, op_fixed=None):
     """Host-side batch: per job (n, k, op, cover, payload, stego input,
-    expected status/len/outputs) from the oracle."""
+    expected status/len/outputs) from the oracle.  k_fixed / op_fixed give
+    every job that k / op."""
     g = inputs.rng(seed)
     jobs = []
     for i in range(count):
@@ -32,6 +33,8 @@ def _mixed_batch(count, seed):
             n = int(g.integers(200_000, 3_000_000))
         k = int(g.integers(1, 9))
         op = OP_EMBED if g.integers(0, 2) == 0 else OP_EXTRACT
+        k = k if k_fixed is None else k_fixed
+        op = op if op_fixed is None else op_fixed
         cover = inputs.random_bytes(n, seed, i, 1)
         cap = oracle.capacity(n, k)
         job = {"n": n, "k": k, "op": op, "cover": cover}
@@ -187,6 +190,20 @@ def test_plan_errors():
             plan.set_jobs(batch.make_jobs(5))  # more than max_jobs
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("op", [OP_EMBED, OP_EXTRACT])
+@pytest.mark.parametrize("k", range(1, 9))
+def test_uniform_class_plans(k, op):
+    """A plan whose jobs all share one (op, k) runs the kernel compiled for
+    that pair only: oracle parity with invalid jobs, default and tiny tiles."""
+    jobs = _mixed_batch(30, 2300 + 10 * k + op, k_fixed=k, op_fixed=op)
+    _run_and_check(jobs)
+    old_cfg, old_tv = batch.tune_get()
+    try:
+        _run_and_check(jobs, tile_vectors=64)
+    finally:
+        batch.tune_set(old_cfg["block"], old_cfg["unroll"], old_cfg["blocks_per_cu"], old_cfg["nontemporal"], old_tv)
 
 
 def test_plan_kinds_and_named_calls():
