@@ -621,6 +621,38 @@ def main():
     ceil = bench_ceiling(api, L, covers, stegos[1], msgs[1], outs[1], [ls[0, j] for j in range(SETS)], dev)
     ceil["embed_k1_of_ceiling"] = round(ceil["embed_k1_mix"]["us_median"] / per["embed_k1"]["us_median"], 4)
     ceil["extract_k1_of_ceiling"] = round(ceil["extract_k1_mix"]["us_median"] / per["extract_k1"]["us_median"], 4)
+    # the same comparison inside the step sequence: steps alternate between
+    # the k = 1 embed and the reference embed-mix stream in its place (into a
+    # scratch buffer, so that every other launch of the step is unchanged)
+    from paper_0912_0947_amd._lib import REF_EMBED_MIX
+    shape = ceil["embed_k1_mix"]["shape"]
+    side = torch.empty(n // 8, dtype=torch.uint8, device=dev)
+    inputs.fill_uniform(side, 1901)
+    scratch = torch.empty(n, dtype=torch.uint8, device=dev)
+    seq = {"embed": [], "ref": []}
+    pairs = make_events(16, [("embed", 1)])
+    for it in range(16):
+        j, jx = it % SETS, (it + 1) % SETS
+        use_ref = it % 2 == 1
+        for ki, k in enumerate(KS):
+            if k == 1:
+                L.lsb_time_next_launch(*pairs[it][("embed", 1)])
+                if use_ref:
+                    api.stream_reference(REF_EMBED_MIX, covers[j], scratch, side, block=shape["block"],
+                                         unroll=shape["unroll"], grid=shape["grid"])
+                else:
+                    api.embed(covers[j], msgs[k], k, out=stegos[k][j])
+            else:
+                api.embed(covers[j], msgs[k], k, out=stegos[k][j])
+            api.extract(stegos[k][jx], k, out=outs[k][jx], len_status=ls[ki, jx])
+    torch.cuda.synchronize()
+    for it in range(2, 16):  # the first two steps warm up
+        a, b = pairs[it][("embed", 1)]
+        seq["ref" if it % 2 else "embed"].append(a.elapsed_time(b) * 1e3)
+    e_us, r_us = statistics.median(seq["embed"]), statistics.median(seq["ref"])
+    ceil["in_sequence"] = {"embed_k1_us": round(e_us, 2), "embed_k1_mix_us": round(r_us, 2),
+                           "embed_k1_of_ceiling": round(r_us / e_us, 4)}
+    del side, scratch
     result["stream_ceiling"] = ceil
 
     if not args.no_batched:
