@@ -27,7 +27,7 @@ struct PlanHeader {
     uint64_t n_jobs;
     uint64_t total_tiles;
     uint64_t tile_vectors;
-    uint64_t reserved;
+    uint64_t next_tile;  // tile counter of the persistent kernel; the upload resets it to 0
 };
 
 struct DevJob {
@@ -163,15 +163,27 @@ template <int UNR, bool NT, int CLS>
 __global__ void __launch_bounds__(1024, UNR == 1 ? 8 : (UNR == 2 ? 6 : 4))
     lsb_batch_kernel(const PlanHeader *hdr, const DevJob *jobs, const uint8_t *cover_arena, uint8_t *stego_arena,
                      uint8_t *msg_arena, const uint32_t *len_dev, const int32_t *status_dev) {
+    // Blocks take tiles from one counter in arrival order, so the tiles in
+    // flight at any moment are neighbours in the arenas (a static b, b + G,
+    // ... order lets blocks drift apart over the run).  Thread 0 requests the
+    // next tile while the block works on the current one; the answer goes
+    // through a double-buffered LDS slot, read after the tile's barrier.
+    __shared__ uint64_t grabbed[2];
+    unsigned long long *counter = (unsigned long long *)&const_cast<PlanHeader *>(hdr)->next_tile;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
     const uint32_t n_waves = blockDim.x >> 6;
     const uint64_t n_jobs = hdr->n_jobs;
     const uint64_t total = hdr->total_tiles;
     const uint64_t tile_vectors = hdr->tile_vectors;
+    if (threadIdx.x == 0) grabbed[0] = atomicAdd(counter, 1ull);
+    __syncthreads();
+    uint64_t tile = grabbed[0];
     uint64_t j = 0;
-    for (uint64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
-        // largest j with jobs[j].tile_begin <= tile (entry n_jobs holds total > tile)
+    for (uint32_t it = 1; tile < total; ++it) {  // `tile` is block-uniform
+        if (threadIdx.x == 0) grabbed[it & 1u] = atomicAdd(counter, 1ull);
+        // largest j with jobs[j].tile_begin <= tile (entry n_jobs holds total > tile);
+        // a block's tiles only grow, so the search runs forward
         for (;;) {
             const uint64_t idx = j + 1 + lane;
             const uint64_t tb = idx <= n_jobs ? jobs[idx].tile_begin : ~0ull;
@@ -181,15 +193,17 @@ __global__ void __launch_bounds__(1024, UNR == 1 ? 8 : (UNR == 2 ? 6 : 4))
             if (cnt < 64) break;
         }
         const DevJob J = jobs[j];
-        if (J.status != LSB_OK) continue;
+        bool run = J.status == LSB_OK;
         uint32_t len = 0;
-        if (J.op == LSB_OP_EXTRACT) {
-            if (status_dev[j] != LSB_OK) continue;
+        if (run && J.op == LSB_OP_EXTRACT) {
+            run = status_dev[j] == LSB_OK;
             len = len_dev[j];
         }
-        const uint64_t v_begin = (tile - J.tile_begin) * tile_vectors;
-        run_tile<UNR, NT, CLS>(J, v_begin, tile_vectors, cover_arena, stego_arena, msg_arena, len, wave, n_waves,
-                               lane);
+        if (run)
+            run_tile<UNR, NT, CLS>(J, (tile - J.tile_begin) * tile_vectors, tile_vectors, cover_arena, stego_arena,
+                                   msg_arena, len, wave, n_waves, lane);
+        __syncthreads();
+        tile = grabbed[it & 1u];
     }
 }
 
