@@ -36,7 +36,7 @@ struct DevJob {
     uint32_t len;
     uint8_t k, op;
     int16_t status;  // host-validated status (embed); extract: decoded on device
-    uint64_t reserved;
+    uint64_t tile_vectors;  // vectors per tile of this job
 };
 static_assert(sizeof(DevJob) == 64, "DevJob is one 64-byte record");
 
@@ -175,7 +175,6 @@ __global__ void __launch_bounds__(1024, UNR == 1 ? 8 : (UNR == 2 ? 6 : 4))
     const uint32_t n_waves = blockDim.x >> 6;
     const uint64_t n_jobs = hdr->n_jobs;
     const uint64_t total = hdr->total_tiles;
-    const uint64_t tile_vectors = hdr->tile_vectors;
     if (threadIdx.x == 0) grabbed[0] = atomicAdd(counter, 1ull);
     __syncthreads();
     uint64_t tile = grabbed[0];
@@ -200,8 +199,8 @@ __global__ void __launch_bounds__(1024, UNR == 1 ? 8 : (UNR == 2 ? 6 : 4))
             len = len_dev[j];
         }
         if (run)
-            run_tile<UNR, NT, CLS>(J, (tile - J.tile_begin) * tile_vectors, tile_vectors, cover_arena, stego_arena,
-                                   msg_arena, len, wave, n_waves, lane);
+            run_tile<UNR, NT, CLS>(J, (tile - J.tile_begin) * J.tile_vectors, J.tile_vectors, cover_arena,
+                                   stego_arena, msg_arena, len, wave, n_waves, lane);
         __syncthreads();
         tile = grabbed[it & 1u];
     }
@@ -434,7 +433,12 @@ int lsb_plan_update(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
             if (v_stream < vectors) vectors = v_stream;
             if ((uint64_t)J.k * J.n < 32) vectors = 0;
         }
-        tiles += ceil_div(vectors, (uint64_t)tv);
+        // an extract tile moves about half the bytes of an embed tile (no
+        // stego write), so it covers twice the vectors to carry the same
+        // traffic per job lookup
+        const uint64_t jtv = op == LSB_OP_EMBED ? (uint64_t)tv : 2 * (uint64_t)tv;
+        D.tile_vectors = jtv;
+        tiles += ceil_div(vectors, jtv);
     }
     DevJob &S = d[n_jobs];  // sentinel
     memset(&S, 0, sizeof S);
