@@ -13,6 +13,7 @@
 // prologue kernel (per-job status; header decode for extract jobs),
 // persistent kernel}.  The graph is built once per plan; later runs only
 // update the copy size and kernel arguments in the executable graph.
+#include <stddef.h>
 #include <string.h>
 
 #include <mutex>
@@ -23,12 +24,19 @@
 
 namespace lsb {
 
+// The tile counter has a 128-byte cache line of its own: sharing a line with
+// the job records that every block reads made each atomic contend with those
+// reads (a one-job batch ran at 40 % of a many-job batch).
 struct PlanHeader {
     uint64_t n_jobs;
     uint64_t total_tiles;
     uint64_t tile_vectors;
+    uint64_t pad0[13];
     uint64_t next_tile;  // tile counter of the persistent kernel; the upload resets it to 0
+    uint64_t pad1[15];
 };
+static_assert(sizeof(PlanHeader) == 256 && offsetof(PlanHeader, next_tile) == 128,
+              "counter on its own line, job records 256-byte aligned");
 
 struct DevJob {
     uint64_t cover_off, stego_off, msg_off, n, msg_cap;
