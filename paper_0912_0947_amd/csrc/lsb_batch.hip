@@ -4,10 +4,10 @@
 // The paper loops on the host over the rows of an image (Section VI steps
 // 4-5 split the data across rows; Section VII steps 3-4 likewise), paying a
 // copy and a launch per row.  Here every cover of a batch is a job, each job
-// is cut into tiles of T 16-byte vectors, and one persistent grid walks the
-// global tile list: block b takes tiles b, b + G, b + 2G, ...  A tile of job
-// j starts at field 16*T*t, so k*t0 is always a whole number of bytes and no
-// two tiles share an output byte.
+// is cut into tiles of T 16-byte vectors (2T for extract jobs), and one
+// persistent grid walks the global tile list, each block taking the next
+// tile from a counter.  A tile of job j starts at field 16*T*t, so k*t0 is
+// always a whole number of bytes and no two tiles share an output byte.
 //
 // Graph of one run: {H2D copy of the job table from pinned host memory,
 // prologue kernel (per-job status; header decode for extract jobs),
@@ -276,8 +276,8 @@ struct lsb_plan {
 };
 
 static void destroy_graph(lsb_plan *p) {
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
     p->exec = nullptr;
     p->graph = nullptr;
 }
@@ -361,9 +361,10 @@ int lsb_plan_create(lsb_plan **out, const lsb_job *jobs, int n_jobs, int op) {
     e = hipHostMalloc((void **)&p->host, p->table_bytes, hipHostMallocDefault);
     if (e != hipSuccess) return delete p, fail(LSB_E_NOMEM, "lsb_plan_create: hipHostMalloc failed");
     e = hipMalloc((void **)&p->dev, p->table_bytes);
-    if (e != hipSuccess) return hipHostFree(p->host), delete p, fail(LSB_E_NOMEM, "lsb_plan_create: hipMalloc failed");
+    if (e != hipSuccess)
+        return (void)hipHostFree(p->host), delete p, fail(LSB_E_NOMEM, "lsb_plan_create: hipMalloc failed");
     e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
-    if (e != hipSuccess) return hipFree(p->dev), hipHostFree(p->host), delete p, hip_fail(e, "hipEventCreate");
+    if (e != hipSuccess) return (void)hipFree(p->dev), (void)hipHostFree(p->host), delete p, hip_fail(e, "hipEventCreate");
     memset(p->host, 0, p->table_bytes);
     p->used_bytes = sizeof(PlanHeader) + sizeof(DevJob);
     if (jobs) {
@@ -482,7 +483,8 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
     if (((uintptr_t)cover_arena | (uintptr_t)stego_arena | (uintptr_t)msg_arena) & 255)
         return fail(LSB_E_ARG, "lsb_plan_run: arena base pointers must be 256-byte aligned");
     int dev = -1;
-    hipGetDevice(&dev);
+    const hipError_t de = hipGetDevice(&dev);
+    if (de != hipSuccess) return hip_fail(de, "hipGetDevice");
     if (dev != p->device) return fail(LSB_E_ARG, "lsb_plan_run: plan belongs to device %d, current is %d", p->device, dev);
     lsb_launch_cfg cfg;
     int64_t tv;
@@ -542,11 +544,12 @@ int lsb_extract_batch(lsb_plan *p, const uint8_t *stego_arena, uint8_t *msg_aren
 
 void lsb_plan_destroy(lsb_plan *p) {
     if (!p) return;
-    if (p->ran) hipEventSynchronize(p->done);
+    // teardown: nothing useful can be done with a failure here
+    if (p->ran) (void)hipEventSynchronize(p->done);
     destroy_graph(p);
-    if (p->done) hipEventDestroy(p->done);
-    if (p->dev) hipFree(p->dev);
-    if (p->host) hipHostFree(p->host);
+    if (p->done) (void)hipEventDestroy(p->done);
+    if (p->dev) (void)hipFree(p->dev);
+    if (p->host) (void)hipHostFree(p->host);
     delete p;
 }
 

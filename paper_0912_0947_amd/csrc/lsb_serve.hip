@@ -111,13 +111,14 @@ class HipExecutor : public Executor {
     }
     ~HipExecutor() override {
         for (S &s : s_) {
-            if (s.busy && s.done) hipEventSynchronize(s.done);
+            // teardown: nothing useful can be done with a failure here
+            if (s.busy && s.done) (void)hipEventSynchronize(s.done);
             for (lsb_plan *p : s.plan)
                 if (p) lsb_plan_destroy(p);
-            if (s.done) hipEventDestroy(s.done);
-            if (s.stream) hipStreamDestroy(s.stream);
-            if (s.status_host) hipHostFree(s.status_host);
-            if (s.len_host) hipHostFree(s.len_host);
+            if (s.done) (void)hipEventDestroy(s.done);
+            if (s.stream) (void)hipStreamDestroy(s.stream);
+            if (s.status_host) (void)hipHostFree(s.status_host);
+            if (s.len_host) (void)hipHostFree(s.len_host);
         }
     }
     // status_off / len_off: arena offsets of 2*B int32 / uint32 per slot

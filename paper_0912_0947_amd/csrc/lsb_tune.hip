@@ -29,7 +29,7 @@ struct Flush {
         return e == hipSuccess ? LSB_OK : hip_fail(e, "hipMemsetAsync(flush)");
     }
     ~Flush() {
-        if (buf) hipFree(buf);
+        if (buf) (void)hipFree(buf);
     }
 };
 
@@ -53,11 +53,18 @@ extern "C" int lsb_autotune(int op, int k, uint64_t n, uint8_t *cover, uint8_t *
     uint32_t *status = nullptr;
     hipError_t e = hipMalloc((void **)&status, 16);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(status)");
-    hipEvent_t ev0, ev1;
-    hipEventCreate(&ev0);
-    hipEventCreate(&ev1);
-    hipEventRecord(ev0, stream);  // both events exist in a recorded state before the first timing
-    hipEventRecord(ev1, stream);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    e = hipEventCreate(&ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ev1);
+    // both events exist in a recorded state before the first timing
+    if (e == hipSuccess) e = hipEventRecord(ev0, stream);
+    if (e == hipSuccess) e = hipEventRecord(ev1, stream);
+    if (e != hipSuccess) {
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        (void)hipFree(status);
+        return hip_fail(e, "hipEventCreate/Record(autotune)");
+    }
 
     // For extract, the stego buffer must carry a full-capacity stream.
     Span base{};
@@ -115,7 +122,11 @@ extern "C" int lsb_autotune(int op, int k, uint64_t n, uint8_t *cover, uint8_t *
                             break;
                         }
                         float ms = 0;
-                        hipEventElapsedTime(&ms, ev0, ev1);
+                        e = hipEventElapsedTime(&ms, ev0, ev1);
+                        if (e != hipSuccess) {
+                            rc = hip_fail(e, "hipEventElapsedTime(autotune)");
+                            break;
+                        }
                         total += ms;
                     }
                     const double t = total / reps;
@@ -124,9 +135,9 @@ extern "C" int lsb_autotune(int op, int k, uint64_t n, uint8_t *cover, uint8_t *
                         best_c = cfg;
                     }
                 }
-    hipEventDestroy(ev0);
-    hipEventDestroy(ev1);
-    hipFree(status);
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    (void)hipFree(status);
     if (rc != LSB_OK) return rc;
     int bucket = 0;
     while (bucket + 1 < kBuckets && (n >> (bucket + 1))) ++bucket;
