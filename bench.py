@@ -159,6 +159,50 @@ def bench_batched(api, batch, dev, log_fn, reps=3):
     return res, (wl, cover, msg)
 
 
+def bench_small_image(api, lib_handle, dev, reps=50):
+    """The 512x512x3 image with a 32 KB message at k = 1 (786,432 cover bytes,
+    a launch-bound size): kernel times from launch-bound events, and the
+    host-observed latency of one embed + extract round trip (both launches
+    and a stream synchronisation), medians over ``reps``."""
+    import torch
+
+    from paper_0912_0947_amd import inputs
+
+    n = 512 * 512 * 3
+    cover = torch.empty(n, dtype=torch.uint8, device=dev)
+    inputs.fill_uniform(cover, 101)
+    msg = torch.empty(32768, dtype=torch.uint8, device=dev)
+    inputs.fill_uniform(msg, 102)
+    stego = torch.empty_like(cover)
+    out = torch.empty_like(msg)
+    ls = torch.zeros(2, dtype=torch.int32, device=dev)
+    ev = {name: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+          for name in ("embed", "extract")}
+    for pairs in ev.values():
+        for a, b in pairs:
+            a.record()
+            b.record()
+    torch.cuda.synchronize()
+    rt = []
+    for r in range(reps + 5):
+        t0 = time.perf_counter()
+        if r >= 5:
+            lib_handle.lsb_time_next_launch(*ev["embed"][r - 5])
+        api.embed(cover, msg, 1, out=stego)
+        if r >= 5:
+            lib_handle.lsb_time_next_launch(*ev["extract"][r - 5])
+        api.extract(stego, 1, out=out, len_status=ls)
+        torch.cuda.current_stream().synchronize()
+        if r >= 5:
+            rt.append((time.perf_counter() - t0) * 1e6)
+    assert torch.equal(out, msg), "small-image round trip failed"
+    res = {"workload": "512x512x3 uniform cover, 32,768-byte message, k=1"}
+    for name, pairs in ev.items():
+        res[name + "_kernel_us"] = round(statistics.median(a.elapsed_time(b) * 1e3 for a, b in pairs), 2)
+    res["roundtrip_us"] = round(statistics.median(rt), 1)
+    return res
+
+
 def bench_paper_layout(api, lib_handle, cover, dev, reps=5):
     """The paper's own layout (2 bits per byte in plane 0, greedy rows, bit
     pair i of byte j in pixel L*i + j) on the 8192x8192x3 cover at full
@@ -615,6 +659,7 @@ def main():
         "per_launch": per,
         "copy_reference": copy_ref,
     }
+    result["small_image"] = bench_small_image(api, L, dev)
     result["paper_layout"] = bench_paper_layout(api, L, covers[0], dev)
     result["quality"] = bench_quality(api, L, covers[0], {k: stegos[k][1] for k in KS}, msgs, dev)
     log("reference streams ...")
