@@ -524,7 +524,7 @@ def main():
                          "k=1 embed only (others timed in a short pass afterwards), or all six")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would take "
+        print("bench.py measures one GPU: this implementation has no multi-GPU path (each GPU would take "
               "its own covers or byte-range shards independently); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
