@@ -196,18 +196,32 @@ int lsb_verify(const uint8_t *cover, const uint8_t *stego, uint64_t n,
  * offset must be a multiple of 256 (LSB_E_ARG otherwise).  The caller
  * guarantees that each job's buffers lie inside the arenas and that no job
  * writes bytes another job reads or writes.
+ *
+ * A job is either a whole cover with its 32-bit length header (flags = 0, as
+ * lsb_embed / lsb_extract) or a raw slice (flags = LSB_JOB_RAW, as
+ * lsb_embed_raw / lsb_extract_raw): the cover buffer holds bytes [t0, t0+n)
+ * of a longer logical cover and msg_off names byte 0 of a logical stream of
+ * stream_bits bits, which several slice jobs of one plan may share (the
+ * frames of a clip, the shards of a cover).  A raw extract job obeys the
+ * alignment rules of lsb_extract_raw; breaking them is LSB_E_ARG for the
+ * whole call.  Header jobs leave t0 and stream_bits at 0.
  */
+enum { LSB_JOB_RAW = 1 };
+
 typedef struct lsb_job {
-    uint64_t cover_off; /* embed: cover input (cover arena)                  */
-    uint64_t stego_off; /* embed: stego output; extract: stego input         */
-    uint64_t msg_off;   /* embed: message input; extract: message output     */
-    uint64_t n;         /* cover bytes                                       */
-    uint64_t msg_cap;   /* extract: output capacity in bytes (embed: unused) */
-    uint32_t len;       /* embed: message length (extract: unused)           */
-    uint8_t k;          /* bits per cover byte, 1..8                         */
-    uint8_t op;         /* LSB_OP_EMBED or LSB_OP_EXTRACT (LSB_OP_MIXED plans) */
-    uint16_t reserved;  /* must be 0                                         */
-} lsb_job;              /* 48 bytes */
+    uint64_t cover_off;   /* embed: cover input (cover arena)                  */
+    uint64_t stego_off;   /* embed: stego output; extract: stego input         */
+    uint64_t msg_off;     /* embed: message / stream input; extract: output    */
+    uint64_t n;           /* cover bytes of this job's buffer                  */
+    uint64_t msg_cap;     /* header extract: output capacity in bytes          */
+    uint64_t t0;          /* raw: logical field index of buffer byte 0         */
+    uint64_t stream_bits; /* raw: bits of the logical stream                   */
+    uint32_t len;         /* header embed: message length                      */
+    uint8_t k;            /* bits per cover byte, 1..8                         */
+    uint8_t op;           /* LSB_OP_EMBED or LSB_OP_EXTRACT (LSB_OP_MIXED plans) */
+    uint8_t flags;        /* 0 or LSB_JOB_RAW                                  */
+    uint8_t reserved;     /* must be 0                                         */
+} lsb_job;                /* 64 bytes */
 
 typedef struct lsb_plan lsb_plan;
 
@@ -224,16 +238,18 @@ typedef struct lsb_plan lsb_plan;
 int lsb_plan_create(lsb_plan **plan, const lsb_job *jobs_host, int n_jobs, int op);
 
 /* Replace the plan's job list (n_jobs <= the n_jobs given at creation),
- * keeping its graph.  Validates every job on the host: a job with bad k or
- * offsets is LSB_E_ARG for the whole call; an embed job whose len exceeds its
+ * keeping its graph.  Validates every job on the host: a job with bad k,
+ * offsets, flags or raw-slice alignment is LSB_E_ARG for the whole call; a
+ * header embed job whose len exceeds its
  * capacity is not an error of the call: it gets status LSB_E_CAPACITY and no
  * work.  Waits for the plan's previous run to have read the job table. */
 int lsb_plan_update(lsb_plan *plan, const lsb_job *jobs_host, int n_jobs);
 
 /* Run every job of the plan on `stream`.  For job j: status_dev[j] <- LSB_OK
- * or its error; for extract jobs len_dev[j] <- decoded length (len_dev may
- * be NULL if the plan has no extract job).  Results are identical to one
- * lsb_embed / lsb_extract call per job. */
+ * or its error; for extract jobs len_dev[j] <- decoded length, 0 for raw
+ * slices (len_dev may be NULL if the plan has no extract job).  Results are
+ * identical to one lsb_embed / lsb_extract call per job (raw slices:
+ * lsb_embed_raw / lsb_extract_raw). */
 int lsb_plan_run(lsb_plan *plan, const uint8_t *cover_arena,
                  uint8_t *stego_arena, uint8_t *msg_arena, uint32_t *len_dev,
                  int32_t *status_dev, void *stream);

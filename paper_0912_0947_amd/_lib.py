@@ -21,9 +21,10 @@ E_BUFFER = -4
 E_HIP = -5
 E_NOMEM = -6
 OP_EMBED = 0
-REF_COPY, REF_EMBED_MIX, REF_EXTRACT_MIX = 0, 1, 2
 OP_EXTRACT = 1
 OP_MIXED = 2
+JOB_RAW = 1  # lsb_job.flags: raw slice, no header
+REF_COPY, REF_EMBED_MIX, REF_EXTRACT_MIX = 0, 1, 2
 
 ERROR_NAMES = {
     OK: "LSB_OK", E_ARG: "LSB_E_ARG", E_CAPACITY: "LSB_E_CAPACITY", E_HEADER: "LSB_E_HEADER",
@@ -43,11 +44,12 @@ class LaunchCfg(ctypes.Structure):
 class Job(ctypes.Structure):
     _fields_ = [("cover_off", ctypes.c_uint64), ("stego_off", ctypes.c_uint64),
                 ("msg_off", ctypes.c_uint64), ("n", ctypes.c_uint64),
-                ("msg_cap", ctypes.c_uint64), ("len", ctypes.c_uint32),
-                ("k", ctypes.c_uint8), ("op", ctypes.c_uint8), ("reserved", ctypes.c_uint16)]
+                ("msg_cap", ctypes.c_uint64), ("t0", ctypes.c_uint64), ("stream_bits", ctypes.c_uint64),
+                ("len", ctypes.c_uint32), ("k", ctypes.c_uint8), ("op", ctypes.c_uint8),
+                ("flags", ctypes.c_uint8), ("reserved", ctypes.c_uint8)]
 
 
-assert ctypes.sizeof(Job) == 48
+assert ctypes.sizeof(Job) == 64
 
 
 class ServerCfg(ctypes.Structure):

@@ -7,12 +7,13 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import OP_EMBED, OP_EXTRACT, OP_MIXED, Job, LaunchCfg, check, lib
+from ._lib import JOB_RAW, OP_EMBED, OP_EXTRACT, OP_MIXED, Job, LaunchCfg, check, lib
 
 ALIGN = 256
 
 JOB_DTYPE = np.dtype([("cover_off", "<u8"), ("stego_off", "<u8"), ("msg_off", "<u8"), ("n", "<u8"),
-                      ("msg_cap", "<u8"), ("len", "<u4"), ("k", "u1"), ("op", "u1"), ("reserved", "<u2")])
+                      ("msg_cap", "<u8"), ("t0", "<u8"), ("stream_bits", "<u8"), ("len", "<u4"), ("k", "u1"),
+                      ("op", "u1"), ("flags", "u1"), ("reserved", "u1")])
 assert JOB_DTYPE.itemsize == ctypes.sizeof(Job)
 
 
@@ -108,4 +109,5 @@ def tune_set(block: int, unroll: int, blocks_per_cu: int, nontemporal: int, tile
     check(lib().lsb_batch_tune_set(ctypes.byref(cfg), int(tile_vectors)))
 
 
-__all__ = ["Plan", "make_jobs", "align_up", "JOB_DTYPE", "OP_EMBED", "OP_EXTRACT", "tune_get", "tune_set"]
+__all__ = ["Plan", "make_jobs", "align_up", "JOB_DTYPE", "JOB_RAW", "OP_EMBED", "OP_EXTRACT", "OP_MIXED", "tune_get",
+           "tune_set"]

@@ -6,8 +6,11 @@
 // copy and a launch per row.  Here every cover of a batch is a job, each job
 // is cut into tiles of T 16-byte vectors (2T for extract jobs), and one
 // persistent grid walks the global tile list, each block taking the next
-// tile from a counter.  A tile of job j starts at field 16*T*t, so k*t0 is
-// always a whole number of bytes and no two tiles share an output byte.
+// tile from a counter.  Tile t of a job starts 16*T*t fields after the job's
+// first field, a whole number of stream bytes, so no two tiles of a job share
+// an output byte.  A job is a whole cover with its length header or a raw
+// slice [t0, t0 + n) of a longer logical cover; slices of one stream may be
+// spread over many jobs (the frames of a clip).
 //
 // Graph of one run: {H2D copy of the job table from pinned host memory,
 // prologue kernel (per-job status; header decode for extract jobs),
@@ -18,35 +21,10 @@
 
 #include <mutex>
 #include <new>
-#include <utility>
 
-#include "lsb_host.hpp"
+#include "lsb_batch_device.hpp"
 
 namespace lsb {
-
-// The tile counter has a 128-byte cache line of its own: sharing a line with
-// the job records that every block reads made each atomic contend with those
-// reads (a one-job batch ran at 40 % of a many-job batch).
-struct PlanHeader {
-    uint64_t n_jobs;
-    uint64_t total_tiles;
-    uint64_t tile_vectors;
-    uint64_t pad0[13];
-    uint64_t next_tile;  // tile counter of the persistent kernel; the upload resets it to 0
-    uint64_t pad1[15];
-};
-static_assert(sizeof(PlanHeader) == 256 && offsetof(PlanHeader, next_tile) == 128,
-              "counter on its own line, job records 256-byte aligned");
-
-struct DevJob {
-    uint64_t cover_off, stego_off, msg_off, n, msg_cap;
-    uint64_t tile_begin;  // tiles of jobs before this one; entry n_jobs = total
-    uint32_t len;
-    uint8_t k, op;
-    int16_t status;  // host-validated status (embed); extract: decoded on device
-    uint64_t tile_vectors;  // vectors per tile of this job
-};
-static_assert(sizeof(DevJob) == 64, "DevJob is one 64-byte record");
 
 // Prologue: one wave per job writes the job's status (and decoded length).
 __global__ void __launch_bounds__(256)
@@ -60,13 +38,13 @@ __global__ void __launch_bounds__(256)
         const DevJob J = jobs[j];
         uint32_t len = J.len;
         int status = J.status;
-        if (J.op == LSB_OP_EXTRACT && status == LSB_OK) {
+        if (J.op == LSB_OP_EXTRACT && !J.raw && status == LSB_OK) {
             len = 0;
             status = LSB_E_HEADER;
             if ((uint64_t)J.k * J.n >= 32) {
                 len = decode_header(stego_arena + J.stego_off, J.k, lane);
                 if (4 + (uint64_t)len > room_bytes(J.n, J.k)) status = LSB_E_HEADER;
-                else if ((uint64_t)len > J.msg_cap) status = LSB_E_BUFFER;
+                else if ((uint64_t)len > J.cap_bits) status = LSB_E_BUFFER;
                 else status = LSB_OK;
             }
         }
@@ -77,158 +55,9 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-// One tile of a job: ranges with k known at compile time, then the walk
-// over the tile's vectors.
-template <int K, int UNR, bool NT>
-__device__ __forceinline__ void embed_tile(const Span &s, uint64_t v_begin, uint64_t tile_vectors, uint32_t wave,
-                                           uint32_t n_waves, uint32_t lane) {
-    const Ranges r = embed_ranges<K>(s);
-    uint64_t v_end = v_begin + tile_vectors;
-    if (v_end > r.count) v_end = r.count;
-    if (v_begin < v_end) embed_walk<K, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane);
-}
-
-template <int K, int UNR, bool NT>
-__device__ __forceinline__ void extract_tile(const Span &s, uint64_t v_begin, uint64_t tile_vectors, uint32_t wave,
-                                             uint32_t n_waves, uint32_t lane) {
-    const Ranges r = extract_ranges<K>(s);
-    uint64_t v_end = v_begin + tile_vectors;
-    if (v_end > r.count) v_end = r.count;
-    if (v_begin < v_end) extract_walk<K, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane);
-}
-
-// CLS = 0: the tile's (op, k) is read from its job and dispatched by a switch
-// over all sixteen walkers; CLS = 1 + 8*op + (k - 1): every job of the plan
-// has that (op, k), and only its walker is compiled in.
-template <int UNR, bool NT, int CLS>
-__device__ __forceinline__ void run_tile(const DevJob &J, uint64_t v_begin, uint64_t tile_vectors,
-                                         const uint8_t *cover_arena, uint8_t *stego_arena, uint8_t *msg_arena,
-                                         uint32_t len, uint32_t wave, uint32_t n_waves, uint32_t lane) {
-    Span s{};
-    s.n = J.n;
-    s.t0 = 0;
-    s.k = J.k;
-    s.hdr_len = 4;
-    s.words = 1;  // offsets are multiples of 256: stream side is dword aligned
-    if constexpr (CLS > 0) {
-        constexpr int OP = (CLS - 1) / 8, K = (CLS - 1) % 8 + 1;
-        if constexpr (OP == LSB_OP_EMBED) {
-            s.src = cover_arena + J.cover_off;
-            s.dst = stego_arena + J.stego_off;
-            s.body = msg_arena + J.msg_off;
-            s.bits = 8 * (4 + (uint64_t)J.len);
-            s.hdr = J.len;
-            embed_tile<K, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane);
-        } else {
-            s.src = stego_arena + J.stego_off;
-            s.out = msg_arena + J.msg_off;
-            s.bits = 8 * (4 + (uint64_t)len);
-            extract_tile<K, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane);
-        }
-        return;
-    }
-    if (J.op == LSB_OP_EMBED) {
-        s.src = cover_arena + J.cover_off;
-        s.dst = stego_arena + J.stego_off;
-        s.body = msg_arena + J.msg_off;
-        s.bits = 8 * (4 + (uint64_t)J.len);
-        s.hdr = J.len;
-        switch (J.k) {
-            case 1: embed_tile<1, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 2: embed_tile<2, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 3: embed_tile<3, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 4: embed_tile<4, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 5: embed_tile<5, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 6: embed_tile<6, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 7: embed_tile<7, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            default: embed_tile<8, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-        }
-    } else {
-        s.src = stego_arena + J.stego_off;
-        s.out = msg_arena + J.msg_off;
-        s.bits = 8 * (4 + (uint64_t)len);
-        switch (J.k) {
-            case 1: extract_tile<1, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 2: extract_tile<2, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 3: extract_tile<3, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 4: extract_tile<4, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 5: extract_tile<5, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 6: extract_tile<6, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 7: extract_tile<7, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            default: extract_tile<8, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-        }
-    }
-}
-
-// Persistent kernel.  Every wave of a block works on the block's tile; the
-// job of a tile is found by a forward search over the tile prefix that 64
-// lanes do in one step (jobs only move forward as the tile id grows).  All
-// sixteen (op, k) walkers are inlined behind one switch, which on its own
-// needs about 90 VGPRs (5 waves per SIMD); the launch bound asks for 8 waves
-// per SIMD at one vector per lane (41 VGPRs) and 6 at two (75 VGPRs), with no
-// spills.
-template <int UNR, bool NT, int CLS>
-__global__ void __launch_bounds__(1024, UNR == 1 ? 8 : (UNR == 2 ? 6 : 4))
-    lsb_batch_kernel(const PlanHeader *hdr, const DevJob *jobs, const uint8_t *cover_arena, uint8_t *stego_arena,
-                     uint8_t *msg_arena, const uint32_t *len_dev, const int32_t *status_dev) {
-    // Blocks take tiles from one counter in arrival order, so the tiles in
-    // flight at any moment are neighbours in the arenas (a static b, b + G,
-    // ... order lets blocks drift apart over the run).  Thread 0 requests the
-    // next tile while the block works on the current one; the answer goes
-    // through a double-buffered LDS slot, read after the tile's barrier.
-    __shared__ uint64_t grabbed[2];
-    unsigned long long *counter = (unsigned long long *)&const_cast<PlanHeader *>(hdr)->next_tile;
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wave = threadIdx.x >> 6;
-    const uint32_t n_waves = blockDim.x >> 6;
-    const uint64_t n_jobs = hdr->n_jobs;
-    const uint64_t total = hdr->total_tiles;
-    if (threadIdx.x == 0) grabbed[0] = atomicAdd(counter, 1ull);
-    __syncthreads();
-    uint64_t tile = grabbed[0];
-    uint64_t j = 0;
-    for (uint32_t it = 1; tile < total; ++it) {  // `tile` is block-uniform
-        if (threadIdx.x == 0) grabbed[it & 1u] = atomicAdd(counter, 1ull);
-        // largest j with jobs[j].tile_begin <= tile (entry n_jobs holds total > tile);
-        // a block's tiles only grow, so the search runs forward
-        for (;;) {
-            const uint64_t idx = j + 1 + lane;
-            const uint64_t tb = idx <= n_jobs ? jobs[idx].tile_begin : ~0ull;
-            const uint64_t below = __ballot(tb <= tile);
-            const uint32_t cnt = (uint32_t)__popcll(below);
-            j += cnt;
-            if (cnt < 64) break;
-        }
-        const DevJob J = jobs[j];
-        bool run = J.status == LSB_OK;
-        uint32_t len = 0;
-        if (run && J.op == LSB_OP_EXTRACT) {
-            run = status_dev[j] == LSB_OK;
-            len = len_dev[j];
-        }
-        if (run)
-            run_tile<UNR, NT, CLS>(J, (tile - J.tile_begin) * J.tile_vectors, J.tile_vectors, cover_arena,
-                                   stego_arena, msg_arena, len, wave, n_waves, lane);
-        __syncthreads();
-        tile = grabbed[it & 1u];
-    }
-}
-
-typedef void (*BatchFn)(const PlanHeader *, const DevJob *, const uint8_t *, uint8_t *, uint8_t *, const uint32_t *,
-                        const int32_t *);
-
-template <int UNR, bool NT, int... C>
-static BatchFn batch_fn_of(int cls, std::integer_sequence<int, C...>) {
-    static const BatchFn table[] = {lsb_batch_kernel<UNR, NT, C>...};
-    return table[cls];
-}
-
-// Kernel for a launch shape and plan class (0 = mixed jobs).
-static BatchFn batch_fn(int unroll, int nt, int cls) {
-    using Classes = std::make_integer_sequence<int, 17>;
-    if (unroll == 1) return nt ? batch_fn_of<1, true>(cls, Classes{}) : batch_fn_of<1, false>(cls, Classes{});
-    if (unroll == 2) return nt ? batch_fn_of<2, true>(cls, Classes{}) : batch_fn_of<2, false>(cls, Classes{});
-    return nt ? batch_fn_of<4, true>(cls, Classes{}) : batch_fn_of<4, false>(cls, Classes{});
+// Kernel for a launch shape, plan class and raw-slice support.
+static BatchFn batch_fn(int unroll, int nt, int cls, bool raw) {
+    return raw ? batch_fn_raw(unroll, nt, cls) : batch_fn_for<false>(unroll, nt, cls);
 }
 
 // Batched-kernel configuration (global, read at each run).
@@ -247,6 +76,7 @@ struct lsb_plan {
     int op_mode = LSB_OP_MIXED;  // LSB_OP_EMBED / LSB_OP_EXTRACT: every job of that kind
     bool has_extract = false;
     bool has_embed = false;
+    bool has_raw = false;  // some job is a raw slice: the raw-capable kernels run
     int cls = 0;  // 1 + 8*op + (k-1) when every job shares (op, k), else 0
     uint64_t total_tiles = 0;
     size_t table_bytes = 0;  // bytes of header + (max_jobs + 1) records
@@ -399,6 +229,23 @@ int lsb_plan_update(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
             return fail(LSB_E_ARG, "job %d: arena offsets must be multiples of 256", i);
         if (J.n > (1ull << 48)) return fail(LSB_E_ARG, "job %d: n out of range", i);
         if (J.reserved) return fail(LSB_E_ARG, "job %d: reserved field must be 0", i);
+        if (J.flags & ~LSB_JOB_RAW) return fail(LSB_E_ARG, "job %d: unknown flags 0x%x", i, (unsigned)J.flags);
+        if (!(J.flags & LSB_JOB_RAW)) {
+            if (J.t0 || J.stream_bits) return fail(LSB_E_ARG, "job %d: t0/stream_bits set on a header job", i);
+            continue;
+        }
+        if (J.t0 > (1ull << 56) || J.stream_bits > (1ull << 60))
+            return fail(LSB_E_ARG, "job %d: t0/stream_bits out of range", i);
+        const uint8_t op = p->op_mode == LSB_OP_MIXED ? J.op : (uint8_t)p->op_mode;
+        if (op == LSB_OP_EXTRACT) {
+            // slices of one stream may not share an output byte
+            const uint64_t begin = (uint64_t)J.k * J.t0;
+            uint64_t end = (uint64_t)J.k * (J.t0 + J.n);
+            if (end > J.stream_bits) end = J.stream_bits;
+            if (begin % 8) return fail(LSB_E_ARG, "job %d: raw extract with k*t0 not byte aligned", i);
+            if (begin < end && end % 8 && end != J.stream_bits)
+                return fail(LSB_E_ARG, "job %d: raw extract ends inside a stream byte", i);
+        }
     }
     // the previous run's upload must have read the mirror before it changes
     if (p->ran) {
@@ -408,7 +255,7 @@ int lsb_plan_update(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
     PlanHeader *h = (PlanHeader *)p->host;
     DevJob *d = (DevJob *)(p->host + sizeof(PlanHeader));
     uint64_t tiles = 0;
-    bool has_extract = false, has_embed = false;
+    bool has_extract = false, has_embed = false, has_raw = false;
     for (int i = 0; i < n_jobs; ++i) {
         const lsb_job &J = jobs[i];
         const uint8_t op = p->op_mode == LSB_OP_MIXED ? J.op : (uint8_t)p->op_mode;
@@ -418,14 +265,32 @@ int lsb_plan_update(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
         D.stego_off = J.stego_off;
         D.msg_off = J.msg_off;
         D.n = J.n;
-        D.msg_cap = J.msg_cap;
-        D.len = J.len;
+        D.raw = (J.flags & LSB_JOB_RAW) ? 1 : 0;
+        has_raw |= D.raw != 0;
+        D.len = D.raw ? 0 : J.len;  // what the prologue reports in len_dev
         D.k = J.k;
         D.op = op;
         D.tile_begin = tiles;
         D.status = LSB_OK;
         uint64_t vectors = ceil_div(J.n, 16);
-        if (op == LSB_OP_EMBED) {
+        if (D.raw) {
+            D.t0 = J.t0;
+            if (op == LSB_OP_EMBED) {
+                has_embed = true;
+                D.cap_bits = J.stream_bits;  // stream bits past the slice fall back to copies
+            } else {
+                has_extract = true;
+                const uint64_t begin = (uint64_t)J.k * J.t0;
+                uint64_t end = (uint64_t)J.k * (J.t0 + J.n);
+                if (end > J.stream_bits) end = J.stream_bits;
+                D.cap_bits = end;
+                // only the fields that carry stream bits [begin, end) are read
+                const uint64_t fields = end > begin ? ceil_div(end - begin, (uint64_t)J.k) : 0;
+                const uint64_t v_stream = ceil_div(fields, 16);
+                if (v_stream < vectors) vectors = v_stream;
+            }
+        } else if (op == LSB_OP_EMBED) {
+            D.cap_bits = 0;
             has_embed = true;
             const uint64_t room = room_bytes(J.n, J.k);
             if (room < 4 || (uint64_t)J.len > room - 4) {
@@ -434,6 +299,7 @@ int lsb_plan_update(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
             }
         } else {
             has_extract = true;
+            D.cap_bits = J.msg_cap;
             // worst case: the stream may fill the cover or the output buffer
             const uint64_t room = room_bytes(J.n, J.k);
             const uint64_t cap = room >= 4 ? room - 4 : 0;
@@ -446,7 +312,6 @@ int lsb_plan_update(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
         // stego write), so it covers twice the vectors to carry the same
         // traffic per job lookup
         const uint64_t jtv = op == LSB_OP_EMBED ? (uint64_t)tv : 2 * (uint64_t)tv;
-        D.tile_vectors = jtv;
         tiles += ceil_div(vectors, jtv);
     }
     DevJob &S = d[n_jobs];  // sentinel
@@ -459,6 +324,7 @@ int lsb_plan_update(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
     p->total_tiles = tiles;
     p->has_extract = has_extract;
     p->has_embed = has_embed;
+    p->has_raw = has_raw;
     p->cls = 0;
     if (n_jobs > 0) {
         bool same = true;
@@ -496,7 +362,7 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
     if (tv != p->tile_vectors) return fail(LSB_E_ARG, "lsb_plan_run: tile size changed since lsb_plan_update");
     // a different kernel (shape or job class) cannot be swapped into the
     // executable graph: rebuild it
-    const BatchFn fn = batch_fn(cfg.unroll, cfg.nontemporal, p->cls);
+    const BatchFn fn = batch_fn(cfg.unroll, cfg.nontemporal, p->cls, p->has_raw);
     const bool rebuild = p->exec && (cfg.block != p->cfg.block || fn != p->fn);
     if (rebuild) destroy_graph(p);
     p->cfg = cfg;

@@ -1,0 +1,220 @@
+// lsb_batch_device.hpp -- device side of the batched embed/extract: the job
+// table records and the persistent kernel, shared by the translation unit of
+// header-only plans and the one of plans with raw-slice jobs.
+#pragma once
+
+#include <stddef.h>
+
+#include <utility>
+
+#include "lsb_host.hpp"
+
+namespace lsb {
+
+// The tile counter has a 128-byte cache line of its own: sharing a line with
+// the job records that every block reads made each atomic contend with those
+// reads (a one-job batch ran at 40 % of a many-job batch).
+struct PlanHeader {
+    uint64_t n_jobs;
+    uint64_t total_tiles;
+    uint64_t tile_vectors;
+    uint64_t pad0[13];
+    uint64_t next_tile;  // tile counter of the persistent kernel; the upload resets it to 0
+    uint64_t pad1[15];
+};
+static_assert(sizeof(PlanHeader) == 256 && offsetof(PlanHeader, next_tile) == 128,
+              "counter on its own line, job records 256-byte aligned");
+
+struct DevJob {
+    uint64_t cover_off, stego_off, msg_off, n;
+    uint64_t cap_bits;    // header extract: msg_cap; raw: end bit (embed: stream_bits, extract: e)
+    uint64_t tile_begin;  // tiles of jobs before this one; entry n_jobs = total
+    uint64_t t0;          // raw: logical field index of buffer byte 0; header jobs: 0
+    uint32_t len;
+    uint8_t k, op;
+    int8_t status;  // host-validated status; header extract: decoded on device
+    uint8_t raw;    // 1: raw slice, no header
+};
+static_assert(sizeof(DevJob) == 64, "DevJob is one 64-byte record");
+static_assert(sizeof(lsb_job) == 64 && offsetof(lsb_job, len) == 56, "lsb_job layout of the C ABI");
+
+// One tile of a job: ranges with k known at compile time, then the walk
+// over the tile's vectors.
+template <int K, int UNR, bool NT>
+__device__ __forceinline__ void embed_tile(const Span &s, uint64_t v_begin, uint64_t tile_vectors, uint32_t wave,
+                                           uint32_t n_waves, uint32_t lane) {
+    const Ranges r = embed_ranges<K>(s);
+    uint64_t v_end = v_begin + tile_vectors;
+    if (v_end > r.count) v_end = r.count;
+    if (v_begin < v_end) embed_walk<K, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane);
+}
+
+template <int K, int UNR, bool NT>
+__device__ __forceinline__ void extract_tile(const Span &s, uint64_t v_begin, uint64_t tile_vectors, uint32_t wave,
+                                             uint32_t n_waves, uint32_t lane) {
+    const Ranges r = extract_ranges<K>(s);
+    uint64_t v_end = v_begin + tile_vectors;
+    if (v_end > r.count) v_end = r.count;
+    if (v_begin < v_end) extract_walk<K, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane);
+}
+
+// CLS = 0: the tile's (op, k) is read from its job and dispatched by a switch
+// over all sixteen walkers; CLS = 1 + 8*op + (k - 1): every job of the plan
+// has that (op, k), and only its walker is compiled in.  Header and raw-slice
+// jobs share the walkers: only the span's stream fields differ.  RAW = false
+// compiles the raw-slice case out (the plan has none): the header span's
+// constant t0, header length and dword stream side then fold into the walk.
+template <int UNR, bool NT, int CLS, bool RAW>
+__device__ __forceinline__ void run_tile(const DevJob &J, uint64_t v_begin, uint64_t tile_vectors,
+                                         const uint8_t *cover_arena, uint8_t *stego_arena, uint8_t *msg_arena,
+                                         uint32_t len, uint32_t wave, uint32_t n_waves, uint32_t lane) {
+    Span s{};
+    s.n = J.n;
+    s.t0 = 0;
+    s.k = J.k;
+    s.hdr_len = 4;
+    s.words = 1;  // offsets are multiples of 256: stream side is dword aligned
+    const bool raw = RAW && J.raw;
+    if (raw) {
+        // stream byte 0 sits at a 256-byte aligned offset, so the stream side
+        // is dword aligned exactly when field t0 starts on a 32-bit boundary
+        s.t0 = J.t0;
+        s.hdr_len = 0;
+        s.words = (((uint64_t)J.k * J.t0) & 31u) == 0;
+    }
+    constexpr int OPC = CLS > 0 ? (CLS - 1) / 8 : -1;
+    if (CLS > 0 ? OPC == LSB_OP_EMBED : J.op == LSB_OP_EMBED) {
+        s.src = cover_arena + J.cover_off;
+        s.dst = stego_arena + J.stego_off;
+        s.body = msg_arena + J.msg_off;
+        s.bits = raw ? J.cap_bits : 8 * (4 + (uint64_t)J.len);
+        s.hdr = J.len;
+        if constexpr (CLS > 0) {
+            constexpr int K = (CLS - 1) % 8 + 1;
+            if constexpr (OPC == LSB_OP_EMBED) embed_tile<K, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane);
+            return;
+        }
+        switch (J.k) {
+            case 1: embed_tile<1, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 2: embed_tile<2, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 3: embed_tile<3, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 4: embed_tile<4, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 5: embed_tile<5, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 6: embed_tile<6, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 7: embed_tile<7, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            default: embed_tile<8, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+        }
+    } else {
+        s.src = stego_arena + J.stego_off;
+        s.out = msg_arena + J.msg_off;
+        s.bits = raw ? J.cap_bits : 8 * (4 + (uint64_t)len);
+        if constexpr (CLS > 0) {
+            constexpr int K = (CLS - 1) % 8 + 1;
+            if constexpr (OPC == LSB_OP_EXTRACT) extract_tile<K, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane);
+            return;
+        }
+        switch (J.k) {
+            case 1: extract_tile<1, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 2: extract_tile<2, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 3: extract_tile<3, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 4: extract_tile<4, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 5: extract_tile<5, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 6: extract_tile<6, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            case 7: extract_tile<7, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            default: extract_tile<8, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+        }
+    }
+}
+
+// Waves per SIMD the launch bound asks for.  A 1024-thread block puts 4
+// waves on each SIMD (so at most 128 VGPRs), and anything from 4 to 7 keeps
+// one block per CU; only 8 fits two.  8 at one vector per lane (about 40
+// VGPRs) and 6 at two (75 with all sixteen walkers behind one switch); the
+// raw-capable kernels with the widest walkers (the switch, or k = 1 embed)
+// take 5 (96 VGPRs) at two vectors per lane, where 6 would spill.
+template <int UNR, int CLS, bool RAW>
+constexpr int batch_min_waves() {
+    if constexpr (UNR == 1) return 8;
+    else if constexpr (UNR == 2) return RAW && CLS <= 1 ? 5 : 6;
+    else return 4;
+}
+
+// Persistent kernel.  Every wave of a block works on the block's tile; the
+// job of a tile is found by a forward search over the tile prefix that 64
+// lanes do in one step (jobs only move forward as the tile id grows).
+template <int UNR, bool NT, int CLS, bool RAW>
+__global__ void __launch_bounds__(1024, (batch_min_waves<UNR, CLS, RAW>()))
+    lsb_batch_kernel(const PlanHeader *hdr, const DevJob *jobs, const uint8_t *cover_arena, uint8_t *stego_arena,
+                     uint8_t *msg_arena, const uint32_t *len_dev, const int32_t *status_dev) {
+    // Blocks take tiles from one counter in arrival order, so the tiles in
+    // flight at any moment are neighbours in the arenas (a static b, b + G,
+    // ... order lets blocks drift apart over the run).  Thread 0 requests the
+    // next tile while the block works on the current one; the answer goes
+    // through a double-buffered LDS slot, read after the tile's barrier.
+    __shared__ uint64_t grabbed[2];
+    unsigned long long *counter = (unsigned long long *)&const_cast<PlanHeader *>(hdr)->next_tile;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t n_waves = blockDim.x >> 6;
+    const uint64_t n_jobs = hdr->n_jobs;
+    const uint64_t total = hdr->total_tiles;
+    const uint64_t tv_embed = hdr->tile_vectors;
+    if (threadIdx.x == 0) grabbed[0] = atomicAdd(counter, 1ull);
+    __syncthreads();
+    uint64_t tile = grabbed[0];
+    uint64_t j = 0;
+    for (uint32_t it = 1; tile < total; ++it) {  // `tile` is block-uniform
+        if (threadIdx.x == 0) grabbed[it & 1u] = atomicAdd(counter, 1ull);
+        // largest j with jobs[j].tile_begin <= tile (entry n_jobs holds total > tile);
+        // a block's tiles only grow, so the search runs forward
+        for (;;) {
+            const uint64_t idx = j + 1 + lane;
+            const uint64_t tb = idx <= n_jobs ? jobs[idx].tile_begin : ~0ull;
+            const uint64_t below = __ballot(tb <= tile);
+            const uint32_t cnt = (uint32_t)__popcll(below);
+            j += cnt;
+            if (cnt < 64) break;
+        }
+        const DevJob J = jobs[j];
+        bool run = J.status == LSB_OK;
+        uint32_t len = 0;
+        if (run && J.op == LSB_OP_EXTRACT && !(RAW && J.raw)) {
+            run = status_dev[j] == LSB_OK;
+            len = len_dev[j];
+        }
+        // an extract tile covers twice the vectors of an embed tile
+        const uint64_t tv = J.op == LSB_OP_EXTRACT ? 2 * tv_embed : tv_embed;
+        if (run)
+            run_tile<UNR, NT, CLS, RAW>(J, (tile - J.tile_begin) * tv, tv, cover_arena, stego_arena, msg_arena, len,
+                                   wave, n_waves, lane);
+        __syncthreads();
+        tile = grabbed[it & 1u];
+    }
+}
+
+typedef void (*BatchFn)(const PlanHeader *, const DevJob *, const uint8_t *, uint8_t *, uint8_t *, const uint32_t *,
+                        const int32_t *);
+
+// Kernel table of one launch shape: entry CLS of the class sequence.
+template <int UNR, bool NT, bool RAW, int... C>
+BatchFn batch_fn_of(int cls, std::integer_sequence<int, C...>) {
+    static const BatchFn table[] = {lsb_batch_kernel<UNR, NT, C, RAW>...};
+    return table[cls];
+}
+
+// Kernel for a launch shape and plan class (0 = mixed jobs).
+template <bool RAW>
+BatchFn batch_fn_for(int unroll, int nt, int cls) {
+    using Classes = std::make_integer_sequence<int, 17>;
+    if (unroll == 1)
+        return nt ? batch_fn_of<1, true, RAW>(cls, Classes{}) : batch_fn_of<1, false, RAW>(cls, Classes{});
+    if (unroll == 2)
+        return nt ? batch_fn_of<2, true, RAW>(cls, Classes{}) : batch_fn_of<2, false, RAW>(cls, Classes{});
+    return nt ? batch_fn_of<4, true, RAW>(cls, Classes{}) : batch_fn_of<4, false, RAW>(cls, Classes{});
+}
+
+// Kernels of plans holding raw-slice jobs (instantiated in their own
+// translation unit, which builds in parallel with the header-only one).
+BatchFn batch_fn_raw(int unroll, int nt, int cls);
+
+}  // namespace lsb

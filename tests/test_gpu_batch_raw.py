@@ -1,0 +1,307 @@
+"""GPU parity of raw-slice jobs in the batched path.
+
+A logical cover (a clip of F frames, or one cover cut into shards) carries
+one stream with no header; every frame is a batch job with its own t0, all
+jobs sharing the stream in the message arena.  The stego frames must equal
+the oracle's raw embed of the whole logical cover, cut into frames, and the
+stream extracted frame by frame must equal the oracle's raw extract of the
+whole logical cover."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_0912_0947_amd import api, batch, inputs
+from paper_0912_0947_amd._lib import OK, OP_EMBED, OP_EXTRACT
+
+from gpu_helpers import DEV, assert_bytes_equal, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _clip(frames, frame_n, k, fill, seed):
+    """Logical cover of `frames` frames of `frame_n` bytes and a stream that
+    fills `fill` of the clip's bits (ending inside a frame)."""
+    total = frames * frame_n
+    cover = inputs.random_bytes(total, seed, 0, 1)
+    stream_bits = max(1, int(total * k * fill))
+    stream = inputs.random_bytes((stream_bits + 7) // 8, seed, 0, 2)
+    return cover, stream, stream_bits
+
+
+def _frames_layout(clips):
+    """Job tables (embed, extract) and arena sizes for several clips in one
+    plan: clip c = (frames, frame_n, k, stream_bits); its frames sit one
+    after another in the cover/stego arenas, its stream at its own offset in
+    the message arena."""
+    count = sum(c[0] for c in clips)
+    te, tx = batch.make_jobs(count), batch.make_jobs(count)
+    off_c = off_m = r = 0
+    places = []
+    for frames, frame_n, k, bits in clips:
+        m0 = off_m
+        frame_offs = []
+        for f in range(frames):
+            for t, op in ((te, OP_EMBED), (tx, OP_EXTRACT)):
+                t[r]["cover_off"] = t[r]["stego_off"] = off_c
+                t[r]["msg_off"], t[r]["n"], t[r]["k"], t[r]["op"] = m0, frame_n, k, op
+                t[r]["flags"], t[r]["t0"], t[r]["stream_bits"] = batch.JOB_RAW, f * frame_n, bits
+            frame_offs.append(off_c)
+            off_c += batch.align_up(frame_n)
+            r += 1
+        places.append((frame_offs, m0))
+        off_m = batch.align_up(off_m + (bits + 7) // 8 + 64)
+    return te, tx, places, max(off_c, 1), max(off_m, 1)
+
+
+def _set_tiles(tv):
+    cfg, _ = batch.tune_get()
+    batch.tune_set(cfg["block"], cfg["unroll"], cfg["blocks_per_cu"], cfg["nontemporal"], tv)
+
+
+@pytest.fixture
+def restore_tiles():
+    old_cfg, old_tv = batch.tune_get()
+    yield
+    batch.tune_set(old_cfg["block"], old_cfg["unroll"], old_cfg["blocks_per_cu"], old_cfg["nontemporal"], old_tv)
+
+
+def _embed_extract_clips(specs, seed, plan_op, order_seed=None):
+    """Raw embed, then raw extract, of the clips `specs` = [(frames, frame_n,
+    k, fill)] through one embed plan and one extract plan (kind `plan_op`:
+    the op itself, or OP_MIXED); every frame and stream is checked against
+    the oracle's raw embed / extract of the whole clip.  Returns the device
+    arenas and the layout."""
+    clips, wants = [], []
+    for c, (frames, frame_n, k, fill) in enumerate(specs):
+        cover, stream, bits = _clip(frames, frame_n, k, fill, seed + c)
+        rc, want_stego = oracle.embed_raw(cover, 0, stream, bits, k)
+        assert rc == OK
+        rc, want_stream = oracle.extract_raw(want_stego, 0, bits, k)
+        assert rc == OK
+        clips.append((frames, frame_n, k, bits))
+        wants.append((cover, stream, want_stego, want_stream))
+    te, tx, places, cbytes, mbytes = _frames_layout(clips)
+    cover_h = np.zeros(cbytes, np.uint8)
+    msg_h = np.zeros(mbytes, np.uint8)
+    for (frames, frame_n, k, bits), (offs, m0), (cover, stream, _, _) in zip(clips, places, wants):
+        for f, o in enumerate(offs):
+            cover_h[o:o + frame_n] = cover[f * frame_n:(f + 1) * frame_n]
+        msg_h[m0:m0 + stream.size] = stream
+    count = len(te)
+    order = np.arange(count) if order_seed is None else inputs.rng(order_seed).permutation(count)
+    cover_d = torch.from_numpy(cover_h).to(DEV)
+    stego_d = torch.zeros_like(cover_d)
+    msg_d = torch.from_numpy(msg_h).to(DEV)
+    out_d = torch.full((mbytes,), 0xA5, dtype=torch.uint8, device=DEV)
+    status = torch.full((count,), 99, dtype=torch.int32, device=DEV)
+    lens = torch.full((count,), 7, dtype=torch.int32, device=DEV)
+    pe = batch.Plan(count, OP_EMBED if plan_op != batch.OP_MIXED else plan_op, te[order])
+    px = batch.Plan(count, OP_EXTRACT if plan_op != batch.OP_MIXED else plan_op, tx[order])
+    try:
+        pe.run(cover_d, stego_d, msg_d, lens, status)
+        torch.cuda.synchronize()
+        assert bool((status == OK).all()), status.cpu().numpy()
+        status.fill_(99)
+        px.run(cover_d, stego_d, out_d, lens, status)
+        torch.cuda.synchronize()
+        assert bool((status == OK).all()), status.cpu().numpy()
+        assert bool((lens == 0).all()), "raw extract jobs report length 0"
+    finally:
+        pe.close()
+        px.close()
+    got_stego, got_out = to_host(stego_d), to_host(out_d)
+    for (frames, frame_n, k, bits), (offs, m0), (_, _, want_stego, want_stream) in zip(clips, places, wants):
+        tag = "frames=%d n=%d k=%d bits=%d" % (frames, frame_n, k, bits)
+        for f, o in enumerate(offs):
+            assert_bytes_equal(got_stego[o:o + frame_n], want_stego[f * frame_n:(f + 1) * frame_n],
+                               "%s frame %d stego" % (tag, f))
+        assert_bytes_equal(got_out[m0:m0 + want_stream.size], want_stream, tag + " stream")
+        assert bool((got_out[m0 + want_stream.size:m0 + want_stream.size + 64] == 0xA5).all()), \
+            tag + ": bytes past the stream were written"
+    return cover_d, stego_d, msg_d, out_d, clips, places
+
+
+@pytest.mark.parametrize("plan_op", [OP_EMBED, batch.OP_MIXED], ids=["fixed", "mixed"])
+@pytest.mark.parametrize("k", range(1, 9))
+def test_raw_clip_uniform_plans(k, plan_op, restore_tiles):
+    """Clip of 7 frames of 24,584 bytes (8 * an odd number: frame t0 is byte
+    aligned in the stream for every k but dword aligned only for some
+    frames), stream ending inside frame 4.  Every job shares (op, k), so the
+    kernel specialised for that pair runs, whatever the plan's kind; default
+    and 64-vector tiles."""
+    _embed_extract_clips([(7, 24_584, k, 0.62)], 5100 + 10 * k, plan_op)
+    _set_tiles(64)
+    _embed_extract_clips([(7, 24_584, k, 0.62)], 5100 + 10 * k, plan_op, order_seed=5190 + k)
+
+
+@pytest.mark.parametrize("specs", [
+    [(5, 8, 1, 0.5), (3, 16, 3, 1.0)],                  # tiny frames; a stream that fills its clip exactly
+    [(5, 4104, 2, 0.999), (4, 100_008, 8, 0.3)],        # ragged vectors; stream ends in frame 1
+    [(3, 1_000_000, 5, 0.77), (6, 4096, 4, 0.5), (2, 24, 7, 0.1)],
+])
+def test_raw_clips_generic_kernel(specs, restore_tiles):
+    """Several clips of different k in one plan (so the generic kernel, with
+    every walker behind a switch, runs), shuffled, default and 64-vector
+    tiles."""
+    _embed_extract_clips(specs, 5200 + len(specs), batch.OP_MIXED, order_seed=5250)
+    _set_tiles(64)
+    _embed_extract_clips(specs, 5200 + len(specs), batch.OP_MIXED)
+
+
+def test_raw_embed_any_t0():
+    """Embed slices may start at any t0 (k*t0 not a whole byte): shards of
+    odd sizes at k = 3, 5 and 7 against the oracle over the whole cover."""
+    for k in (3, 5, 7):
+        sizes = [1, 15, 17, 1001, 4097, 33, 70_001]
+        total = sum(sizes)
+        cover = inputs.random_bytes(total, 5300, k, 1)
+        bits = total * k - 5
+        stream = inputs.random_bytes((bits + 7) // 8, 5300, k, 2)
+        rc, want = oracle.embed_raw(cover, 0, stream, bits, k)
+        assert rc == OK
+        t = batch.make_jobs(len(sizes))
+        arena = np.zeros(sum(batch.align_up(s) for s in sizes), np.uint8)
+        off = t0 = 0
+        for i, s in enumerate(sizes):
+            t[i]["cover_off"] = t[i]["stego_off"] = off
+            t[i]["n"], t[i]["k"], t[i]["flags"] = s, k, batch.JOB_RAW
+            t[i]["t0"], t[i]["stream_bits"] = t0, bits
+            arena[off:off + s] = cover[t0:t0 + s]
+            off += batch.align_up(s)
+            t0 += s
+        cover_d = torch.from_numpy(arena).to(DEV)
+        stego_d = torch.zeros_like(cover_d)
+        msg_d = torch.from_numpy(stream).to(DEV)
+        status = torch.full((len(sizes),), 99, dtype=torch.int32, device=DEV)
+        plan = batch.Plan(len(sizes), OP_EMBED, t)
+        try:
+            plan.embed_batch(cover_d, stego_d, msg_d, status)
+            torch.cuda.synchronize()
+        finally:
+            plan.close()
+        assert bool((status == OK).all())
+        got = to_host(stego_d)
+        off = t0 = 0
+        for i, s in enumerate(sizes):
+            assert_bytes_equal(got[off:off + s], want[t0:t0 + s], "k=%d shard %d (t0=%d n=%d)" % (k, i, t0, s))
+            off += batch.align_up(s)
+            t0 += s
+
+
+def test_raw_jobs_equal_single_calls():
+    """Each raw job's output equals lsb_embed_raw / lsb_extract_raw on the
+    same frame."""
+    cover_d, stego_d, msg_d, out_d, clips, places = _embed_extract_clips([(6, 65_544, 2, 0.55)], 5400, OP_EMBED)
+    (frames, frame_n, k, bits), (offs, m0) = clips[0], places[0]
+    nb = (bits + 7) // 8
+    single_out = torch.zeros(nb, dtype=torch.uint8, device=DEV)
+    for f, o in enumerate(offs):
+        single = api.embed_raw(cover_d[o:o + frame_n], f * frame_n, msg_d[m0:], bits, k)
+        assert torch.equal(single, stego_d[o:o + frame_n]), "frame %d" % f
+        api.extract_raw(stego_d[o:o + frame_n], f * frame_n, single_out, bits, k)
+    torch.cuda.synchronize()
+    assert torch.equal(single_out, out_d[m0:m0 + nb])
+
+
+def test_header_and_raw_jobs_in_one_plan():
+    """One mixed plan: header embeds, header extracts, raw embed frames and
+    raw extract frames (of a second clip), in shuffled order."""
+    k = 1
+    frames, frame_n = 4, 12_296
+    clip, stream, bits = _clip(frames, frame_n, k, 0.8, 5500)
+    rc, clip_stego = oracle.embed_raw(clip, 0, stream, bits, k)
+    clip2, stream2, bits2 = _clip(frames, frame_n, k, 0.4, 5501)
+    rc2, clip2_stego = oracle.embed_raw(clip2, 0, stream2, bits2, k)
+    assert rc == rc2 == OK
+    covers = [inputs.random_bytes(n, 5502, i, 1) for i, n in enumerate((5000, 77_777, 300))]
+    msgs = [inputs.random_bytes(n, 5502, i, 2) for i, n in enumerate((100, 9000, 30))]
+    jobs = []  # (row, cover-arena bytes, stego-arena bytes, msg-arena bytes)
+    off_c = 0
+    off_m = batch.align_up(stream.size) + batch.align_up(stream2.size)  # streams at 0 and after
+    rows = batch.make_jobs(2 * frames + 2 * len(covers))
+    r = 0
+    cover_h = np.zeros(64 << 20, np.uint8)
+    stego_h = np.zeros(64 << 20, np.uint8)
+    msg_h = np.zeros(1 << 20, np.uint8)
+    msg_h[:stream.size] = stream
+    s2 = batch.align_up(stream.size)
+    expect = []
+    for f in range(frames):  # raw embed frames of clip 1
+        rows[r]["cover_off"] = rows[r]["stego_off"] = off_c
+        rows[r]["msg_off"], rows[r]["n"], rows[r]["k"], rows[r]["op"] = 0, frame_n, k, OP_EMBED
+        rows[r]["flags"], rows[r]["t0"], rows[r]["stream_bits"] = batch.JOB_RAW, f * frame_n, bits
+        cover_h[off_c:off_c + frame_n] = clip[f * frame_n:(f + 1) * frame_n]
+        expect.append(("stego", off_c, clip_stego[f * frame_n:(f + 1) * frame_n]))
+        off_c += batch.align_up(frame_n)
+        r += 1
+    for f in range(frames):  # raw extract frames of clip 2 into the second stream slot
+        rows[r]["stego_off"] = off_c
+        rows[r]["msg_off"], rows[r]["n"], rows[r]["k"], rows[r]["op"] = s2, frame_n, k, OP_EXTRACT
+        rows[r]["flags"], rows[r]["t0"], rows[r]["stream_bits"] = batch.JOB_RAW, f * frame_n, bits2
+        stego_h[off_c:off_c + frame_n] = clip2_stego[f * frame_n:(f + 1) * frame_n]
+        off_c += batch.align_up(frame_n)
+        r += 1
+    expect.append(("msg", s2, oracle.extract_raw(clip2_stego, 0, bits2, k)[1]))
+    for i, (c, m) in enumerate(zip(covers, msgs)):  # header embeds
+        rows[r]["cover_off"] = rows[r]["stego_off"] = off_c
+        rows[r]["msg_off"], rows[r]["n"], rows[r]["k"], rows[r]["op"], rows[r]["len"] = off_m, c.size, k, OP_EMBED, m.size
+        cover_h[off_c:off_c + c.size] = c
+        msg_h[off_m:off_m + m.size] = m
+        expect.append(("stego", off_c, oracle.embed(c, m, k)[1]))
+        off_c += batch.align_up(c.size)
+        off_m += batch.align_up(m.size)
+        r += 1
+    for i, (c, m) in enumerate(zip(covers, msgs)):  # header extracts of the same messages
+        rows[r]["stego_off"] = off_c
+        rows[r]["msg_off"], rows[r]["n"], rows[r]["k"], rows[r]["op"], rows[r]["msg_cap"] = off_m, c.size, k, OP_EXTRACT, m.size
+        stego_h[off_c:off_c + c.size] = oracle.embed(c, m, k)[1]
+        expect.append(("msg", off_m, m))
+        off_c += batch.align_up(c.size)
+        off_m += batch.align_up(m.size)
+        r += 1
+    order = inputs.rng(5503).permutation(r)
+    cover_d = torch.from_numpy(cover_h[:off_c]).to(DEV)
+    stego_d = torch.from_numpy(stego_h[:off_c]).to(DEV)
+    msg_d = torch.from_numpy(msg_h[:off_m]).to(DEV)
+    status = torch.full((r,), 99, dtype=torch.int32, device=DEV)
+    lens = torch.full((r,), 7, dtype=torch.int32, device=DEV)
+    plan = batch.Plan(r, batch.OP_MIXED, rows[order])
+    try:
+        plan.run(cover_d, stego_d, msg_d, lens, status)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    assert bool((status == OK).all()), status.cpu().numpy()
+    ln = lens.cpu().numpy()
+    for pos, i in enumerate(order):
+        want_len = rows[i]["msg_cap"] if (rows[i]["op"] == OP_EXTRACT and not rows[i]["flags"]) else \
+            (0 if rows[i]["flags"] else rows[i]["len"])
+        assert ln[pos] == want_len, "job %d: len %d want %d" % (i, ln[pos], want_len)
+    st_h, ms_h = to_host(stego_d), to_host(msg_d)
+    for kind, off, want in expect:
+        got = st_h if kind == "stego" else ms_h
+        assert_bytes_equal(got[off:off + want.size], want, "%s at %d" % (kind, off))
+
+
+def test_raw_job_validation():
+    """Unknown flags, t0 on a header job, and raw extract slices that would
+    share an output byte are rejected for the whole call."""
+    plan = batch.Plan(2)
+    try:
+        def one(**kw):
+            t = batch.make_jobs(1)
+            t[0]["n"], t[0]["k"], t[0]["op"], t[0]["flags"] = 96, 3, OP_EXTRACT, batch.JOB_RAW
+            t[0]["t0"], t[0]["stream_bits"] = 8, 10_000
+            for key, v in kw.items():
+                t[0][key] = v
+            return t
+        plan.set_jobs(one())  # bits [24, 312): whole bytes
+        plan.set_jobs(one(op=OP_EMBED, t0=3))  # embed: any t0
+        for bad in (dict(flags=2), dict(flags=0), dict(t0=3), dict(n=100), dict(reserved=1)):
+            with pytest.raises(Exception):
+                plan.set_jobs(one(**bad))
+        plan.set_jobs(one(stream_bits=30))  # ends inside a byte, but at the stream's end
+        plan.set_jobs(one(stream_bits=10))  # slice past the stream's end: no work
+    finally:
+        plan.close()
