@@ -88,6 +88,63 @@ def cpu_baseline(cover_np, msgs):
                       "buffers (%.1f s), single thread" % dt}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline_threads(cover_np, msgs, threads):
+    """The same oracle on `threads` host cores: the cover is cut into shards
+    at multiples of 8 bytes (so every shard's first stream bit k*t0 is byte
+    aligned at every k), and each thread embeds and then extracts its shard
+    as a raw slice of the stream.  Same work and byte counts as the
+    single-thread leg; the stream (header + message) is assembled in the
+    timed region."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import oracle
+    from oracle.ref import stream_of
+
+    n = cover_np.size
+    bounds = [(n * i // threads) // 8 * 8 for i in range(threads)] + [n]
+    shards = [(bounds[i], bounds[i + 1]) for i in range(threads) if bounds[i + 1] > bounds[i]]
+    total = 0
+    outs = {}
+    with ThreadPoolExecutor(len(shards)) as pool:
+        t0 = time.perf_counter()
+        for k in KS:
+            stream = np.frombuffer(stream_of(msgs[k].tobytes()), np.uint8)
+            bits = 8 * stream.size
+            out = np.zeros(stream.size, np.uint8)
+
+            def one(ab, k=k, stream=stream, bits=bits, out=out):
+                a, b = ab
+                rc, stego = oracle.embed_raw(cover_np[a:b], a, stream, bits, k)
+                assert rc == 0
+                rc, _ = oracle.extract_raw(stego, a, bits, k, stream_out=out)
+                assert rc == 0
+
+            list(pool.map(one, shards))
+            outs[k] = out
+            total += embed_bytes(n, msgs[k].size) + extract_bytes(n, msgs[k].size, k)
+        dt = time.perf_counter() - t0
+    for k in KS:  # the decoded header and message must be the input's
+        ln = int.from_bytes(outs[k][:4].tobytes(), "big")
+        assert ln == msgs[k].size and np.array_equal(outs[k][4:], msgs[k]), k
+    return {"value": round(total / dt / 1e9, 4), "unit": "GB/s", "cores": len(shards), "kind": "oracle",
+            "sample": "one full step as the single-thread leg, the cover cut into %d shards of about %d MB "
+                      "run as raw slices on %d threads (%.2f s)" % (len(shards), n // len(shards) >> 20,
+                                                                     len(shards), dt)}
+
+
 def bench_batched(api, batch, dev, log_fn, reps=3):
     """Uneven batch of 4096 covers (about 35 GB): one persistent graph launch
     per op against a loop of one plain launch per cover on one stream."""
@@ -717,6 +774,10 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one step ...")
         result["cpu_baseline"] = cpu_baseline(cover_np, msgs_np)
+        result["cpu_baseline"]["cpu_model"] = cpu_model()
+        threads = max(1, min(16, os.cpu_count() or 1))
+        log("timing the CPU oracle on one step, %d threads ..." % threads)
+        result["cpu_baseline_threads"] = cpu_baseline_threads(cover_np, msgs_np, threads)
     print(json.dumps(result), flush=True)
 
 
