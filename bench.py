@@ -309,41 +309,44 @@ REF_SHAPES = [(256, 1, 0), (512, 1, 0), (1024, 1, 0), (256, 2, 0), (256, 1, 1024
 
 
 def bench_ceiling(api, lib_handle, srcs, dsts, msg1, outs1, ls1, dev, reps=7):
-    """Achievable bandwidth for the traffic mixes of the k = 1 embed (read n
-    + n/8, write n) and extract (read n, write n/8) on this device: plain
-    hand-written streams of the same bytes over the rotating buffer sets, the
-    best of REF_SHAPES, each shape the median of ``reps`` launches timed with
-    launch-bound events.  The k = 1 embed and extract are then timed the same
-    way (same buffers, same rotation) for a like-for-like ratio."""
+    """Achievable bandwidth for the traffic mixes of the embed (read n +
+    nk/8, write n) and extract (read n, write nk/8) kernels at k = 1, 2, 4
+    on this device: plain hand-written streams of the same bytes over the
+    rotating buffer sets, the best of REF_SHAPES, each shape the median of
+    ``reps`` launches timed with launch-bound events.  The k = 1 embed and
+    extract are then timed the same way (same buffers, same rotation) for a
+    like-for-like ratio."""
     import torch
 
     from paper_0912_0947_amd import inputs
     from paper_0912_0947_amd._lib import REF_COPY, REF_EMBED_MIX, REF_EXTRACT_MIX
 
     n = srcs[0].numel()
-    sides = [torch.empty(n // 8, dtype=torch.uint8, device=dev) for _ in srcs]
-    for i, t in enumerate(sides):
-        inputs.fill_uniform(t, 1801 + i)
-    smalls = [torch.empty(n // 8, dtype=torch.uint8, device=dev) for _ in srcs]
-    kinds = [("copy", REF_COPY, 2 * n), ("embed_k1_mix", REF_EMBED_MIX, 2 * n + n // 8),
-             ("extract_k1_mix", REF_EXTRACT_MIX, n + n // 8)]
+    sides = {k: [torch.empty(n * k // 8, dtype=torch.uint8, device=dev) for _ in srcs] for k in KS}
+    for k in KS:
+        for i, t in enumerate(sides[k]):
+            inputs.fill_uniform(t, 1801 + 10 * k + i)
+    smalls = {k: [torch.empty(n * k // 8, dtype=torch.uint8, device=dev) for _ in srcs] for k in KS}
+    kinds = [("copy", REF_COPY, 1, 2 * n)]
+    kinds += [("embed_k%d_mix" % k, REF_EMBED_MIX, k, 2 * n + n * k // 8) for k in KS]
+    kinds += [("extract_k%d_mix" % k, REF_EXTRACT_MIX, k, n + n * k // 8) for k in KS]
     out = {}
     it = 0
-    for name, kind, b in kinds:
+    for name, kind, k, b in kinds:
         best = None
         for block, unroll, grid in REF_SHAPES:
             ms = []
             for r in range(reps + 1):
                 j = it % len(srcs)
                 it += 1
-                dst = smalls[j] if kind == REF_EXTRACT_MIX else dsts[j]
+                dst = smalls[k][j] if kind == REF_EXTRACT_MIX else dsts[j]
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record()
                 e1.record()
                 torch.cuda.synchronize()
                 lib_handle.lsb_time_next_launch(e0, e1)
-                api.stream_reference(kind, srcs[j], dst, sides[j] if kind == REF_EMBED_MIX else None,
-                                     block=block, unroll=unroll, grid=grid)
+                api.stream_reference(kind, srcs[j], dst, sides[k][j] if kind == REF_EMBED_MIX else None,
+                                     block=block, unroll=unroll, grid=grid, k=k)
                 torch.cuda.synchronize()
                 if r:
                     ms.append(e0.elapsed_time(e1))
@@ -352,13 +355,17 @@ def bench_ceiling(api, lib_handle, srcs, dsts, msg1, outs1, ls1, dev, reps=7):
                 best = {"bytes": b, "us_median": round(us, 2), "GBps": round(b / (us * 1e-6) / 1e9, 1),
                         "shape": {"block": block, "unroll": unroll, "grid": grid}}
         out[name] = best
-    # the streams really moved the bytes: spot-check the last embed-mix output
+    # the streams really moved the bytes: spot-check an embed-mix output at k = 1 and 4
     j = (it - 1) % len(srcs)
-    api.stream_reference(REF_EMBED_MIX, srcs[j], dsts[j], sides[j])
-    v = dsts[j][:4096].view(torch.int32).view(-1, 4)
-    w = srcs[j][:4096].view(torch.int32).view(-1, 4).clone()
-    w[:, 0] ^= sides[j][:512].view(torch.int16).to(torch.int32) & 0xFFFF
-    assert torch.equal(v, w), "reference stream output mismatch"
+    for k in (1, 4):
+        api.stream_reference(REF_EMBED_MIX, srcs[j], dsts[j], sides[k][j], k=k)
+        v = dsts[j][:4096].view(torch.int32).view(-1, 4)
+        w = srcs[j][:4096].view(torch.int32).view(-1, 4).clone()
+        if k == 1:
+            w[:, 0] ^= sides[k][j][:512].view(torch.int16).to(torch.int32) & 0xFFFF
+        else:
+            w[:, :2] ^= sides[k][j][:2048].view(torch.int32).view(-1, 2)
+        assert torch.equal(v, w), "reference stream output mismatch (k=%d)" % k
     del sides, smalls
 
     def rotate(fn):
@@ -468,14 +475,18 @@ def bench_video(api, lib_handle, dev, log_fn, frames=600, h=1080, w=1920):
     device-resident whole clip: one lsb_embed launch over the clip;
     device-resident per frame: 600 lsb_embed_raw launches (t0 = f * frame),
     issued from the host and, separately, captured once in a HIP graph;
+    device-resident per frame, batched: the 600 frames as raw-slice jobs of
+    one batched plan (one persistent launch);
     host-streamed: the clip in pinned host memory pipelined through a 4-slot
     device ring, frames alternating over two streams that each copy in, embed
     and copy out, whose rate is bounded by PCIe, not HBM."""
+    import numpy as np
     import torch
 
-    from paper_0912_0947_amd import inputs
+    from paper_0912_0947_amd import batch, inputs
 
     fb = h * w * 3
+    assert fb % batch.ALIGN == 0, "frames must start at 256-byte aligned arena offsets"
     clip = inputs.video_frames(frames, h, w, device=dev).view(-1)
     n = clip.numel()
     ln = n // 8 // 2 - 4
@@ -527,6 +538,23 @@ def bench_video(api, lib_handle, dev, log_fn, frames=600, h=1080, w=1920):
     res["device_per_frame_graph"] = {"launches": frames, "ms": round(best * 1e3, 3),
                                      "GBps": round((2 * n + ln + 4) / best / 1e9, 1)}
     del graph
+    # the same frames as raw-slice jobs of one batched plan: one persistent
+    # launch walks every frame (the clip is the cover arena, frame f at f * fb)
+    jobs = batch.make_jobs(frames)
+    jobs["cover_off"] = jobs["stego_off"] = np.arange(frames, dtype=np.uint64) * fb
+    jobs["n"], jobs["k"], jobs["flags"] = fb, 1, batch.JOB_RAW
+    jobs["t0"] = np.arange(frames, dtype=np.uint64) * fb
+    jobs["stream_bits"] = 8 * (ln + 4)
+    status = torch.full((frames,), 99, dtype=torch.int32, device=dev)
+    plan = batch.Plan(frames, batch.OP_EMBED, jobs)
+    try:
+        per.fill_(7)
+        t = timed(lambda: plan.embed_batch(clip, per, stream, status))
+        assert bool((status == 0).all()) and torch.equal(per, stego), "batched per-frame embed differs"
+    finally:
+        plan.close()
+    res["device_per_frame_batched"] = {"launches": 1, "jobs": frames, "ms": round(t * 1e3, 3),
+                                       "GBps": round((2 * n + ln + 4) / t / 1e9, 1)}
     host = torch.empty(n, dtype=torch.uint8, pin_memory=True)
     host.copy_(clip)
     host_out = torch.empty(n, dtype=torch.uint8, pin_memory=True)
@@ -721,40 +749,53 @@ def main():
     result["quality"] = bench_quality(api, L, covers[0], {k: stegos[k][1] for k in KS}, msgs, dev)
     log("reference streams ...")
     ceil = bench_ceiling(api, L, covers, stegos[1], msgs[1], outs[1], [ls[0, j] for j in range(SETS)], dev)
-    ceil["embed_k1_of_ceiling"] = round(ceil["embed_k1_mix"]["us_median"] / per["embed_k1"]["us_median"], 4)
-    ceil["extract_k1_of_ceiling"] = round(ceil["extract_k1_mix"]["us_median"] / per["extract_k1"]["us_median"], 4)
-    # the same comparison inside the step sequence: steps alternate between
-    # the k = 1 embed and the reference embed-mix stream in its place (into a
-    # scratch buffer, so that every other launch of the step is unchanged)
-    from paper_0912_0947_amd._lib import REF_EMBED_MIX
-    shape = ceil["embed_k1_mix"]["shape"]
-    side = torch.empty(n // 8, dtype=torch.uint8, device=dev)
-    inputs.fill_uniform(side, 1901)
+    # each launch of the step against the rotation-context stream of its own bytes
+    ceil["of_ceiling"] = {key: round(ceil[key + "_mix"]["us_median"] / per[key]["us_median"], 4)
+                          for key in ("%s_k%d" % ok for ok in all_keys)}
+    # the same comparison inside the step sequence: for each launch of the
+    # step in turn, steps alternate between that launch and the reference
+    # stream of its bytes in its place (into scratch buffers, so that every
+    # other launch of the step is unchanged)
+    from paper_0912_0947_amd._lib import REF_EMBED_MIX, REF_EXTRACT_MIX
+    mix_side = {k: torch.empty(n * k // 8, dtype=torch.uint8, device=dev) for k in KS}
+    for k in KS:
+        inputs.fill_uniform(mix_side[k], 1901 + k)
+    mix_out = {k: torch.empty(n * k // 8, dtype=torch.uint8, device=dev) for k in KS}
     scratch = torch.empty(n, dtype=torch.uint8, device=dev)
-    seq = {"embed": [], "ref": []}
-    pairs = make_events(16, [("embed", 1)])
-    for it in range(16):
-        j, jx = it % SETS, (it + 1) % SETS
-        use_ref = it % 2 == 1
-        for ki, k in enumerate(KS):
-            if k == 1:
-                L.lsb_time_next_launch(*pairs[it][("embed", 1)])
-                if use_ref:
-                    api.stream_reference(REF_EMBED_MIX, covers[j], scratch, side, block=shape["block"],
-                                         unroll=shape["unroll"], grid=shape["grid"])
+    seq_steps = 14  # the first two warm up; then kernel and reference alternate
+    in_seq = {}
+    for slot in all_keys:
+        op_s, k_s = slot
+        shape = ceil["%s_k%d_mix" % slot]["shape"]
+        pairs = make_events(seq_steps, [slot])
+        for it in range(seq_steps):
+            j, jx = it % SETS, (it + 1) % SETS
+            use_ref = it % 2 == 1
+            for ki, k in enumerate(KS):
+                if slot == ("embed", k):
+                    L.lsb_time_next_launch(*pairs[it][slot])
+                if slot == ("embed", k) and use_ref:
+                    api.stream_reference(REF_EMBED_MIX, covers[j], scratch, mix_side[k], block=shape["block"],
+                                         unroll=shape["unroll"], grid=shape["grid"], k=k)
                 else:
                     api.embed(covers[j], msgs[k], k, out=stegos[k][j])
-            else:
-                api.embed(covers[j], msgs[k], k, out=stegos[k][j])
-            api.extract(stegos[k][jx], k, out=outs[k][jx], len_status=ls[ki, jx])
-    torch.cuda.synchronize()
-    for it in range(2, 16):  # the first two steps warm up
-        a, b = pairs[it][("embed", 1)]
-        seq["ref" if it % 2 else "embed"].append(a.elapsed_time(b) * 1e3)
-    e_us, r_us = statistics.median(seq["embed"]), statistics.median(seq["ref"])
-    ceil["in_sequence"] = {"embed_k1_us": round(e_us, 2), "embed_k1_mix_us": round(r_us, 2),
-                           "embed_k1_of_ceiling": round(r_us / e_us, 4)}
-    del side, scratch
+                if slot == ("extract", k):
+                    L.lsb_time_next_launch(*pairs[it][slot])
+                if slot == ("extract", k) and use_ref:
+                    api.stream_reference(REF_EXTRACT_MIX, stegos[k][jx], mix_out[k], block=shape["block"],
+                                         unroll=shape["unroll"], grid=shape["grid"], k=k)
+                else:
+                    api.extract(stegos[k][jx], k, out=outs[k][jx], len_status=ls[ki, jx])
+        torch.cuda.synchronize()
+        seq = {"kernel": [], "ref": []}
+        for it in range(2, seq_steps):
+            a, b = pairs[it][slot]
+            seq["ref" if it % 2 else "kernel"].append(a.elapsed_time(b) * 1e3)
+        k_us, r_us = statistics.median(seq["kernel"]), statistics.median(seq["ref"])
+        in_seq["%s_k%d" % slot] = {"kernel_us": round(k_us, 2), "mix_us": round(r_us, 2),
+                                   "of_ceiling": round(r_us / k_us, 4)}
+    ceil["in_sequence"] = in_seq
+    del mix_side, mix_out, scratch
     result["stream_ceiling"] = ceil
 
     if not args.no_batched:

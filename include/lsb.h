@@ -381,23 +381,27 @@ int lsb_time_next_launch(void *start_event, void *stop_event);
 /* Measurement support: reference streams with the traffic mixes of the
  * method's kernels, so that a kernel's duration can be set against a plain
  * stream of the same bytes on the same device.  Computes nothing of the
- * method.  Over the nv = n / 16 vectors of 16 bytes of `src`:
- *   LSB_REF_COPY         dst vector i = src vector i       (read n, write n)
- *   LSB_REF_EMBED_MIX    as COPY with 16-bit side[i] XORed into the first
- *                        dword (read n + n/8, write n: the k = 1 embed mix)
- *   LSB_REF_EXTRACT_MIX  16-bit dst[i] = low half of the XOR of src vector
- *                        i's four dwords (read n, write n/8: the k = 1
- *                        extract mix); side unused
+ * method.  At k bits per cover byte (k in {1, 2, 4}) a 16-byte cover vector
+ * goes with 2k stream bytes.  Over the nv = n / 16 vectors of `src`:
+ *   LSB_REF_COPY         dst vector i = src vector i (read n, write n; k
+ *                        only checked)
+ *   LSB_REF_EMBED_MIX    as COPY with the 2k bytes side[i] XORed into the
+ *                        first dword (k = 4: first two dwords) of the vector
+ *                        (read n + nk/8, write n: the embed mix)
+ *   LSB_REF_EXTRACT_MIX  the 2k bytes dst[i] = for k = 1 the low half, for
+ *                        k = 2 all of the XOR of src vector i's four dwords;
+ *                        for k = 4 {v0 ^ v1, v2 ^ v3} (read n, write nk/8:
+ *                        the extract mix); side unused
  * n must be a multiple of 16; src (and dst for the first two kinds) 16-byte
- * aligned, side and dst 2-byte aligned; dst holds n bytes (n/8 for
- * EXTRACT_MIX) and overlaps no input.  Launch shape: block in {256, 512,
- * 1024}, unroll in {1, 2, 4} vectors in flight per lane (one grid stride
- * apart), grid 0 = enough blocks for one pass, else capped at that.  Device
- * pointers, asynchronous on `stream`; timed like the embed kernel through
- * lsb_time_next_launch.  Errors: LSB_E_ARG. */
+ * aligned, side and the EXTRACT_MIX dst 2k-byte aligned; dst holds n bytes
+ * (nk/8 for EXTRACT_MIX), side nk/8, and dst overlaps no input.  Launch
+ * shape: block in {256, 512, 1024}, unroll in {1, 2, 4} vectors in flight
+ * per lane (one grid stride apart), grid 0 = enough blocks for one pass,
+ * else capped at that.  Device pointers, asynchronous on `stream`; timed
+ * like the embed kernel through lsb_time_next_launch.  Errors: LSB_E_ARG. */
 enum { LSB_REF_COPY = 0, LSB_REF_EMBED_MIX = 1, LSB_REF_EXTRACT_MIX = 2 };
-int lsb_stream_reference(int kind, const uint8_t *src, uint8_t *dst, const uint8_t *side, uint64_t n, int block,
-                         int unroll, uint32_t grid, void *stream);
+int lsb_stream_reference(int kind, int k, const uint8_t *src, uint8_t *dst, const uint8_t *side, uint64_t n,
+                         int block, int unroll, uint32_t grid, void *stream);
 
 /* The same scheduler without a GPU: launches are modelled (a launch of
  * jobs moving B algorithmic bytes finishes launch_us + B / device_gbps after

@@ -112,7 +112,7 @@ SIGNATURES = {
     "lsb_serve_simulate": (_I, [ctypes.POINTER(ServerCfg), _P, _I, _P, ctypes.POINTER(ServeStats),
                                 ctypes.c_double, ctypes.c_double]),
     "lsb_time_next_launch": (_I, [_P, _P]),
-    "lsb_stream_reference": (_I, [_I, _P, _P, _P, _U64, _I, _I, _U32, _P]),
+    "lsb_stream_reference": (_I, [_I, _I, _P, _P, _P, _U64, _I, _I, _U32, _P]),
     "lsb_last_error": (ctypes.c_char_p, []),
     "lsb_version": (ctypes.c_char_p, []),
 }

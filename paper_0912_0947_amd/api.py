@@ -213,19 +213,20 @@ def verify(cover: torch.Tensor, stego: torch.Tensor, msg: torch.Tensor, k: int,
 
 
 def stream_reference(kind: int, src: torch.Tensor, dst: torch.Tensor, side: torch.Tensor | None = None,
-                     block: int = 256, unroll: int = 1, grid: int = 0, stream=None) -> torch.Tensor:
+                     block: int = 256, unroll: int = 1, grid: int = 0, stream=None, k: int = 1) -> torch.Tensor:
     """Reference stream with the traffic mix ``kind`` (REF_COPY, REF_EMBED_MIX,
-    REF_EXTRACT_MIX) over ``src``; a measurement aid that computes nothing of
-    the method.  ``dst`` holds src.numel() bytes (src.numel() // 8 for
-    REF_EXTRACT_MIX); ``side`` holds src.numel() // 8 bytes for REF_EMBED_MIX."""
+    REF_EXTRACT_MIX) of k bits per cover byte (1, 2 or 4) over ``src``; a
+    measurement aid that computes nothing of the method.  ``dst`` holds
+    src.numel() bytes (src.numel() * k // 8 for REF_EXTRACT_MIX); ``side``
+    holds src.numel() * k // 8 bytes for REF_EMBED_MIX."""
     n = src.numel()
-    want = n // 8 if kind == 2 else n
+    want = n * k // 8 if kind == 2 else n
     if dst.numel() != want:
         raise ValueError("dst must hold %d bytes" % want)
-    if kind == 1 and (side is None or side.numel() != n // 8):
-        raise ValueError("side must hold %d bytes" % (n // 8))
+    if kind == 1 and (side is None or side.numel() != n * k // 8):
+        raise ValueError("side must hold %d bytes" % (n * k // 8))
     sp = _u8(side, "side") if side is not None else None
-    check(lib().lsb_stream_reference(kind, _u8(src, "src"), _u8(dst, "dst"), sp, n, block, unroll, grid,
+    check(lib().lsb_stream_reference(kind, k, _u8(src, "src"), _u8(dst, "dst"), sp, n, block, unroll, grid,
                                      _stream_ptr(stream)))
     return dst
 
