@@ -334,6 +334,7 @@ def bench_ceiling(api, lib_handle, srcs, dsts, msg1, outs1, ls1, dev, reps=7):
     it = 0
     for name, kind, k, b in kinds:
         best = None
+        ranked = []
         for block, unroll, grid in REF_SHAPES:
             ms = []
             for r in range(reps + 1):
@@ -351,9 +352,11 @@ def bench_ceiling(api, lib_handle, srcs, dsts, msg1, outs1, ls1, dev, reps=7):
                 if r:
                     ms.append(e0.elapsed_time(e1))
             us = statistics.median(ms) * 1e3
+            ranked.append((us, {"block": block, "unroll": unroll, "grid": grid}))
             if best is None or us < best["us_median"]:
                 best = {"bytes": b, "us_median": round(us, 2), "GBps": round(b / (us * 1e-6) / 1e9, 1),
                         "shape": {"block": block, "unroll": unroll, "grid": grid}}
+        best["next_shapes"] = [sh for _, sh in sorted(ranked, key=lambda x: x[0])[1:3]]
         out[name] = best
     # the streams really moved the bytes: spot-check an embed-mix output at k = 1 and 4
     j = (it - 1) % len(srcs)
@@ -764,9 +767,10 @@ def main():
     scratch = torch.empty(n, dtype=torch.uint8, device=dev)
     seq_steps = 14  # the first two warm up; then kernel and reference alternate
     in_seq = {}
-    for slot in all_keys:
-        op_s, k_s = slot
-        shape = ceil["%s_k%d_mix" % slot]["shape"]
+
+    def alternate(slot, shape):
+        """Median kernel and reference times of `slot` over steps that
+        alternate between the two (reference with launch shape `shape`)."""
         pairs = make_events(seq_steps, [slot])
         for it in range(seq_steps):
             j, jx = it % SETS, (it + 1) % SETS
@@ -791,9 +795,18 @@ def main():
         for it in range(2, seq_steps):
             a, b = pairs[it][slot]
             seq["ref" if it % 2 else "kernel"].append(a.elapsed_time(b) * 1e3)
-        k_us, r_us = statistics.median(seq["kernel"]), statistics.median(seq["ref"])
-        in_seq["%s_k%d" % slot] = {"kernel_us": round(k_us, 2), "mix_us": round(r_us, 2),
-                                   "of_ceiling": round(r_us / k_us, 4)}
+        return statistics.median(seq["kernel"]), statistics.median(seq["ref"])
+
+    for slot in all_keys:
+        # the stream's three best shapes on an idle device, each tried in the sequence
+        mix = ceil["%s_k%d_mix" % slot]
+        best = None
+        for shape in [mix["shape"]] + mix["next_shapes"]:
+            k_us, r_us = alternate(slot, shape)
+            if best is None or r_us < best["mix_us"]:
+                best = {"kernel_us": round(k_us, 2), "mix_us": round(r_us, 2), "of_ceiling": round(r_us / k_us, 4),
+                        "mix_shape": shape}
+        in_seq["%s_k%d" % slot] = best
     ceil["in_sequence"] = in_seq
     del mix_side, mix_out, scratch
     result["stream_ceiling"] = ceil
