@@ -305,3 +305,54 @@ def test_raw_job_validation():
         plan.set_jobs(one(stream_bits=10))  # slice past the stream's end: no work
     finally:
         plan.close()
+
+
+def test_config3_clip_as_batched_frames():
+    """The video workload as the bench times it in one batched launch: 600
+    frames of 1080x1920x3 (3.73 GB) as raw-slice jobs of one plan, k = 1, one
+    stream at 50 % capacity (ends at the end of frame 299).  The stego equals
+    the whole-clip embed; 600 raw extract jobs give the stream back; sampled
+    frames match the oracle."""
+    frames, h, w = 600, 1080, 1920
+    fb = h * w * 3
+    assert fb % batch.ALIGN == 0
+    clip = inputs.video_frames(frames, h, w, device=DEV).view(-1)
+    n = clip.numel()
+    ln = n // 8 // 2 - 4
+    msg = torch.empty(ln, dtype=torch.uint8, device=DEV)
+    inputs.fill_uniform(msg, 303)
+    whole = api.embed(clip, msg, 1)
+    stream = torch.empty(4 + ln, dtype=torch.uint8, device=DEV)
+    stream[:4] = torch.tensor(list(ln.to_bytes(4, "big")), dtype=torch.uint8)
+    stream[4:] = msg
+    bits = 8 * (4 + ln)
+    jobs = batch.make_jobs(frames)
+    jobs["cover_off"] = np.arange(frames, dtype=np.uint64) * fb
+    jobs["stego_off"] = jobs["cover_off"]
+    jobs["n"], jobs["k"], jobs["flags"], jobs["stream_bits"] = fb, 1, batch.JOB_RAW, bits
+    jobs["t0"] = np.arange(frames, dtype=np.uint64) * fb
+    status = torch.full((frames,), 99, dtype=torch.int32, device=DEV)
+    lens = torch.full((frames,), 7, dtype=torch.int32, device=DEV)
+    stego = torch.full_like(clip, 0x5A)
+    back = torch.zeros_like(stream)
+    pe = batch.Plan(frames, OP_EMBED, jobs)
+    px = batch.Plan(frames, OP_EXTRACT, jobs)
+    try:
+        pe.embed_batch(clip, stego, stream, status)
+        torch.cuda.synchronize()
+        assert bool((status == OK).all())
+        assert torch.equal(stego, whole), "batched frames differ from the whole-clip embed"
+        status.fill_(99)
+        px.extract_batch(stego, back, lens, status)
+        torch.cuda.synchronize()
+        assert bool((status == OK).all()) and bool((lens == 0).all())
+        assert torch.equal(back, stream), "batched frame extraction lost the stream"
+    finally:
+        pe.close()
+        px.close()
+    stream_np = to_host(stream)
+    for f in (0, 1, 299, 300, 599):
+        sl = slice(f * fb, (f + 1) * fb)
+        rc, want = oracle.embed_raw(to_host(clip[sl]), f * fb, stream_np, bits, 1)
+        assert rc == OK
+        assert_bytes_equal(to_host(stego[sl]), want, "frame %d vs oracle" % f)
