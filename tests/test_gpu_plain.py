@@ -278,6 +278,47 @@ def test_config3_video_full_clip():
         assert_bytes_equal(to_host(whole[sl]), want, "frame %d vs oracle" % f)
 
 
+@pytest.mark.parametrize("k", [4, 8])
+def test_maximum_message_length(k):
+    """The longest message the 32-bit header allows, 2^32 - 1 bytes, in the
+    smallest cover that holds it (n = 8 (2^32 + 3) / k, so every byte carries
+    the stream and stream offsets pass 2^32).  Closed forms over the whole
+    buffer: at k = 8 the stego is the stream BE32(len) || msg itself; at k = 4
+    its high nibbles are the cover's and its low nibbles the stream's, most
+    significant first.  The last 64 KiB also match the oracle, and extraction
+    reports length 2^32 - 1 with the message whole."""
+    ln = 0xFFFFFFFF
+    n = 8 * (4 + ln) // k
+    assert api.capacity(n, k) == ln and api.capacity(n - 1, k) == ln - 1
+    cover = torch.empty(n, dtype=torch.uint8, device=DEV)
+    inputs.fill_uniform(cover, 2101)
+    msg = torch.empty(ln, dtype=torch.uint8, device=DEV)
+    inputs.fill_uniform(msg, 2102)
+    stego = api.embed(cover, msg, k)
+    ff = torch.full((4,), 0xFF, dtype=torch.uint8, device=DEV)
+    if k == 8:
+        assert torch.equal(stego[:4], ff) and torch.equal(stego[4:], msg)
+    else:
+        assert torch.equal(stego & 0xF0, cover & 0xF0)
+        assert torch.equal(stego[0:8:2] & 0x0F, ff >> 4) and torch.equal(stego[1:8:2] & 0x0F, ff & 0x0F)
+        assert torch.equal(stego[8::2] & 0x0F, msg >> 4)
+        assert torch.equal(stego[9::2] & 0x0F, msg & 0x0F)
+    m = 1 << 16
+    t0 = n - m
+    s_first = k * t0 // 8  # stream bytes of the last m fields: all message bytes
+    tail = to_host(msg[s_first - 4:])
+    # the oracle takes the stream from byte 0: pass the tail as a shorter
+    # stream shifted to start at field 0 (t0' = 0, same bits)
+    rc, want = oracle.embed_raw(to_host(cover[t0:]), 0, tail, 8 * tail.size, k)
+    assert rc == 0
+    assert_bytes_equal(to_host(stego[t0:]), want, "k=%d last %d bytes" % (k, m))
+    del cover
+    out, ls = api.extract(stego, k)
+    ls = ls.cpu().numpy()
+    assert ls[1] == OK and int(np.uint32(ls[0])) == ln
+    assert torch.equal(out[:ln], msg)
+
+
 @pytest.mark.parametrize("k", [1, 8])
 def test_cover_beyond_4gib(k):
     """A cover of 2^32 + 4109 bytes (byte offsets past 32 bits): the stego
