@@ -37,6 +37,14 @@
  *   - Any alignment is accepted.  The fast kernels need the cover and stego
  *     (or stego) pointers 16-byte aligned; otherwise a per-byte kernel runs
  *     (same results, lower bandwidth).
+ *   - Threads: every call may be made from several host threads at once,
+ *     except that one lsb_plan is used by one thread at a time (distinct
+ *     plans are independent).  The shared state is the launch-configuration
+ *     tables (guarded; a launch uses the entry current at its call) and
+ *     per-thread state (error message, lsb_time_next_launch events,
+ *     lsb_extract_sync buffer).
+ *   - Devices: calls launch on the current HIP device; a plan belongs to the
+ *     device current when it was created.
  */
 #ifndef LSB_H
 #define LSB_H
@@ -249,7 +257,10 @@ int lsb_plan_update(lsb_plan *plan, const lsb_job *jobs_host, int n_jobs);
  * or its error; for extract jobs len_dev[j] <- decoded length, 0 for raw
  * slices (len_dev may be NULL if the plan has no extract job).  Results are
  * identical to one lsb_embed / lsb_extract call per job (raw slices:
- * lsb_embed_raw / lsb_extract_raw). */
+ * lsb_embed_raw / lsb_extract_raw).  The arena base pointers must be
+ * 256-byte aligned.  LSB_E_ARG if the current device is not the plan's, or
+ * if the batch tile size (lsb_batch_tune_set) changed since the plan's last
+ * lsb_plan_update (update the plan again first). */
 int lsb_plan_run(lsb_plan *plan, const uint8_t *cover_arena,
                  uint8_t *stego_arena, uint8_t *msg_arena, uint32_t *len_dev,
                  int32_t *status_dev, void *stream);
@@ -300,8 +311,10 @@ int lsb_autotune(int op, int k, uint64_t n, uint8_t *cover, uint8_t *stego,
                  uint8_t *msg, int reps, lsb_launch_cfg *best,
                  double *best_us, void *stream);
 
-/* Batched-kernel configuration: tile size in 16-byte vectors per tile, the
- * kernel's block/unroll/nontemporal choice and its grid cap. */
+/* Batched-kernel configuration: tile size in 16-byte vectors per embed tile
+ * (extract tiles span twice as many; a multiple of 64 in [64, 2^30]), the
+ * kernel's block/unroll/nontemporal choice and its grid cap.  Plans read the
+ * tile size at lsb_plan_update and the rest at each run. */
 int lsb_batch_tune_get(lsb_launch_cfg *cfg, int64_t *tile_vectors);
 int lsb_batch_tune_set(const lsb_launch_cfg *cfg, int64_t tile_vectors);
 
