@@ -287,3 +287,32 @@ def test_config4_full_scale():
         rc, want = oracle.embed(to_host(cover[c0:c0 + n]), to_host(msg[m0:m0 + ln]), k)
         assert rc == 0
         assert_bytes_equal(to_host(stego[c0:c0 + n]), want, "cfg4 job %d vs oracle" % i)
+
+
+def test_in_place_and_empty_plans():
+    """Embed jobs whose stego is their own cover (one arena for both, same
+    offsets) give the out-of-place bytes; a plan with no jobs runs as a
+    no-op and can be filled afterwards."""
+    wl = BatchWorkload(16, oracle.capacity, seed=431, lo=64, hi=900)
+    cover, stego, msg, out = wl.allocate(DEV)
+    status = torch.full((wl.count,), 99, dtype=torch.int32, device=DEV)
+    plan = batch.Plan(wl.count, OP_EMBED)
+    try:
+        plan.update(batch.make_jobs(0))
+        plan.embed_batch(cover, stego, msg, status)  # nothing to do
+        torch.cuda.synchronize()
+        assert bool((status == 99).all())
+        plan.update(wl.jobs(OP_EMBED))
+        stego.zero_()
+        plan.embed_batch(cover, stego, msg, status)
+        torch.cuda.synchronize()
+        assert bool((status == OK).all())
+        buf = cover.clone()
+        plan.embed_batch(buf, buf, msg, status)  # in place
+        torch.cuda.synchronize()
+        assert bool((status == OK).all())
+        for i in range(wl.count):
+            o, n = int(wl.cover_off[i]), int(wl.n[i])
+            assert torch.equal(buf[o:o + n], stego[o:o + n]), "job %d in place" % i
+    finally:
+        plan.close()
