@@ -1,0 +1,62 @@
+"""The benchmark's contract, checked on the CPU: one GPU only, a loud exit
+without a GPU, the algorithmic byte counts it divides by, and the threaded
+oracle leg (raw-slice shards) on a small cover."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import bench
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _run(*args):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], capture_output=True, text=True,
+                          timeout=300, cwd=ROOT)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = _run("--gpus", "2")
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and not r.stdout.strip()
+
+
+def test_no_gpu_exits_loudly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    r = _run("--steps", "1", "--warmup", "0")
+    assert r.returncode != 0 and "needs a GPU" in r.stderr
+    assert not r.stdout.strip(), "no JSON line without a measurement"
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 8])
+def test_algorithmic_bytes(k):
+    """Embed moves the cover in and the stego out plus the stream (2n + |S|);
+    extract reads the F = ceil(8|S| / k) carrying bytes and writes the
+    message.  At full capacity of the 8192x8192x3 cover, F = n exactly for
+    k dividing 8."""
+    n = 8192 * 8192 * 3
+    ln = oracle.capacity(n, k)
+    s = 4 + ln
+    assert bench.embed_bytes(n, ln) == 2 * n + s
+    f = -(-8 * s // k)
+    assert bench.extract_bytes(n, ln, k) == f + ln
+    if 8 % k == 0:
+        assert f == n
+
+
+def test_threaded_oracle_leg():
+    """The threaded CPU baseline cuts the cover into shards at multiples of 8
+    bytes and runs each as a raw slice: its decoded stream checks out at
+    every k of the workload, and the figure is a rate over the same bytes."""
+    n = 3 * 65536 + 8 * 37
+    cover = np.random.default_rng(7).integers(0, 256, n, dtype=np.uint8)
+    msgs = {k: np.random.default_rng(10 + k).integers(0, 256, oracle.capacity(n, k), dtype=np.uint8)
+            for k in bench.KS}
+    r = bench.cpu_baseline_threads(cover, msgs, 5)
+    assert r["kind"] == "oracle" and r["cores"] == 5 and r["value"] > 0 and r["unit"] == "GB/s"
