@@ -51,9 +51,9 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "plain_8192x8192x3_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0912_0947_amd", "csrc", f) for f in ("lsb_device.hpp", "lsb_plain.hip")]
 
 
-def stored_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter profile, or
-    None when the kernel sources or the selected kernel changed since."""
+def _traffic_profile():
+    """The committed counter profile's entries, or None when the kernel
+    sources changed since it was taken."""
     import hashlib
     import re
 
@@ -62,9 +62,41 @@ def stored_traffic(kernel: str):
     text = open(TRAFFIC_PROFILE).read()
     got = dict(re.findall(r"^(kernel|source_sha256|traffic_bytes_per_launch): (.+)$", text, flags=re.M))
     sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
-    if got.get("source_sha256") != sha or got.get("kernel") != kernel:
+    if got.get("source_sha256") != sha:
+        return None
+    got["launches"] = {key: (name, int(b)) for key, name, b in
+                       re.findall(r"^launch (\w+): (.+) = (\d+)$", text, flags=re.M)}
+    return got
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` (the k = 1 embed) from the committed
+    counter profile, or None when the kernel sources or the selected kernel
+    changed since."""
+    got = _traffic_profile()
+    if got is None or got.get("kernel") != kernel:
         return None
     return int(got["traffic_bytes_per_launch"])
+
+
+def stored_launch_traffic(launch: str, kernel: str):
+    """HBM bytes per launch for one launch of the step (e.g. "extract_k2"), or
+    None when the sources or the selected kernel changed since."""
+    got = _traffic_profile()
+    if got is None:
+        return None
+    name, b = got["launches"].get(launch, (None, None))
+    return b if name == kernel else None
+
+
+def launch_kernel_name(api, op: str, k: int, n: int) -> str:
+    """Name of the plain kernel the tuned table selects for one launch."""
+    cfg = api.tune_get(api.OP_EMBED if op == "embed" else api.OP_EXTRACT, k, n)
+    nt = "true" if cfg["nontemporal"] else "false"
+    if op == "embed":
+        return "lsb_embed_kernel<%d, %d, %s>" % (k, cfg["unroll"], nt)
+    ballot = "true" if (k == 1 and cfg["pack"]) else "false"
+    return "lsb_extract_kernel<%d, %d, %s, %s>" % (k, cfg["unroll"], nt, ballot)
 
 
 def cpu_baseline(cover_np, msgs):
@@ -728,13 +760,23 @@ def main():
     value = step_bytes * args.steps / wall / 1e9
     dom = per["embed_k1"]
     achieved = dom["bytes"] / (dom["us_mean"] * 1e-6) / 1e9
-    cfg = api.tune_get(api.OP_EMBED, 1, n)
-    kernel = "lsb_embed_kernel<1, %d, %s>" % (cfg["unroll"], "true" if cfg["nontemporal"] else "false")
+    kernel = launch_kernel_name(api, "embed", 1, n)
     traffic = stored_traffic(kernel)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kernel + " (k=1 embed, 8192x8192x3 cover, full-capacity message)",
                 "algorithmic_bytes_per_launch": dom["bytes"], "launch_us_mean": dom["us_mean"]}
+
+    # every launch of the step against the same peak, with its share of the step
+    step_us = wall / args.steps * 1e6
+    by_launch = {}
+    for (op, k) in all_keys:
+        key = "%s_k%d" % (op, k)
+        name = launch_kernel_name(api, op, k, n)
+        a = per[key]["bytes"] / (per[key]["us_mean"] * 1e-6) / 1e9
+        by_launch[key] = {"kernel": name, "achieved": round(a, 1), "frac": round(a / HBM_PEAK_GBS, 4),
+                          "traffic": stored_launch_traffic(key, name), "us_mean": per[key]["us_mean"],
+                          "share_of_step": round(per[key]["us_mean"] / step_us, 4)}
 
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -744,6 +786,7 @@ def main():
                                "capacity, k=1,2,4, one embed + one extract launch per k per step",
                    "cover_bytes": n, "ks": list(KS), "buffer_sets": SETS},
         "roofline": roofline,
+        "roofline_by_launch": by_launch,
         "per_launch": per,
         "copy_reference": copy_ref,
     }
