@@ -97,7 +97,7 @@ def _load():
     global _lib
     with _lock:
         if _lib is None:
-            override = os.environ.get("LSB_ORACLE_LIB")  # mutation tests only
+            override = os.environ.get("LSB_ORACLE_LIB")  # mutation tests, sanitizer builds
             if override:
                 _lib = _bind(override)
             else:
