@@ -1,0 +1,112 @@
+/* abi_check.c -- the C ABI of liblsb.so used from plain C (and C++): every
+ * entry point of lsb.h is referenced with its declared type, the record
+ * layouts that bindings rely on are fixed, and the host-only calls run
+ * without a GPU (capacity, tuning tables, the serving scheduler on its
+ * modelled clock).  Prints "ok" on success. */
+#include <stddef.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "lsb.h"
+
+#ifdef __cplusplus
+#define STATIC_ASSERT static_assert
+#else
+#define STATIC_ASSERT _Static_assert
+#endif
+
+STATIC_ASSERT(sizeof(lsb_job) == 64, "lsb_job is 64 bytes");
+STATIC_ASSERT(offsetof(lsb_job, msg_cap) == 32 && offsetof(lsb_job, t0) == 40 &&
+                  offsetof(lsb_job, stream_bits) == 48 && offsetof(lsb_job, len) == 56 &&
+                  offsetof(lsb_job, flags) == 62,
+              "lsb_job field offsets");
+STATIC_ASSERT(sizeof(lsb_launch_cfg) == 20, "lsb_launch_cfg is five int32");
+STATIC_ASSERT(sizeof(lsb_server_cfg) == 48, "lsb_server_cfg is 48 bytes");
+STATIC_ASSERT(sizeof(lsb_request) == 48, "lsb_request is 48 bytes");
+STATIC_ASSERT(sizeof(lsb_result) == 56, "lsb_result is 56 bytes");
+STATIC_ASSERT(sizeof(lsb_serve_stats) == 104, "lsb_serve_stats is 104 bytes");
+
+typedef void (*any_fn)(void);
+
+/* Every entry point, through its declared type (a mismatch fails to compile). */
+static const any_fn entry_points[] = {
+    (any_fn)lsb_capacity,       (any_fn)lsb_embed,           (any_fn)lsb_extract,
+    (any_fn)lsb_extract_sync,   (any_fn)lsb_embed_raw,       (any_fn)lsb_extract_raw,
+    (any_fn)lsb_paper_capacity, (any_fn)lsb_paper_embed,     (any_fn)lsb_paper_extract,
+    (any_fn)lsb_embed_plane,    (any_fn)lsb_extract_plane,   (any_fn)lsb_sse,
+    (any_fn)lsb_video_embed_host, (any_fn)lsb_verify,        (any_fn)lsb_plan_create,
+    (any_fn)lsb_plan_update,    (any_fn)lsb_plan_run,        (any_fn)lsb_embed_batch,
+    (any_fn)lsb_extract_batch,  (any_fn)lsb_plan_tiles,      (any_fn)lsb_plan_destroy,
+    (any_fn)lsb_tune_get,       (any_fn)lsb_tune_set,        (any_fn)lsb_autotune,
+    (any_fn)lsb_batch_tune_get, (any_fn)lsb_batch_tune_set,  (any_fn)lsb_serve,
+    (any_fn)lsb_time_next_launch, (any_fn)lsb_stream_reference, (any_fn)lsb_serve_simulate,
+    (any_fn)lsb_last_error,     (any_fn)lsb_version,
+};
+
+static int check(int cond, const char *what) {
+    if (!cond) fprintf(stderr, "FAILED: %s (%s)\n", what, lsb_last_error());
+    return cond ? 0 : 1;
+}
+
+int main(void) {
+    int bad = 0;
+    size_t i;
+    for (i = 0; i < sizeof entry_points / sizeof entry_points[0]; ++i) bad += check(entry_points[i] != NULL, "symbol");
+
+    /* capacity: floor(n*k/8) - 4, capped by the 32-bit header */
+    bad += check(lsb_capacity(786432, 1) == 98300, "capacity 512x512x3 at k = 1");
+    bad += check(lsb_capacity(201326592, 4) == 100663292, "capacity 8192x8192x3 at k = 4");
+    bad += check(lsb_capacity(1ull << 40, 8) == 0xFFFFFFFFll, "capacity capped at 2^32 - 1");
+    bad += check(lsb_capacity(31, 1) == LSB_E_CAPACITY, "no room for the header");
+    bad += check(lsb_capacity(100, 9) == LSB_E_ARG && lsb_last_error()[0] != '\0', "k outside 1..8");
+    bad += check(lsb_paper_capacity(7, 1024) == 7 * 256, "paper-layout capacity");
+    bad += check(lsb_version() != NULL && strlen(lsb_version()) > 0, "version string");
+
+    /* tuning tables round trip */
+    {
+        lsb_launch_cfg c, back;
+        int64_t tv = 0;
+        bad += check(lsb_tune_get(LSB_OP_EMBED, 3, 1u << 20, &c) == LSB_OK, "tune_get");
+        bad += check(lsb_tune_set(LSB_OP_EMBED, 3, 20, &c) == LSB_OK, "tune_set");
+        bad += check(lsb_tune_get(LSB_OP_EMBED, 3, 1u << 20, &back) == LSB_OK && memcmp(&c, &back, sizeof c) == 0,
+                     "tune round trip");
+        bad += check(lsb_batch_tune_get(&c, &tv) == LSB_OK && tv >= 64, "batch tune_get");
+        c.block = 100;
+        bad += check(lsb_tune_set(LSB_OP_EMBED, 3, 20, &c) == LSB_E_ARG, "invalid block refused");
+    }
+
+    /* the serving scheduler on its modelled clock: four embeds, then two
+     * extracts of the first two stegos */
+    {
+        lsb_server_cfg cfg;
+        lsb_request req[6];
+        lsb_result res[6];
+        lsb_serve_stats st;
+        memset(&cfg, 0, sizeof cfg);
+        memset(req, 0, sizeof req);
+        cfg.arena_bytes = 1u << 24;
+        cfg.max_batch = 4;
+        cfg.n_slots = 2;
+        for (i = 0; i < 6; ++i) {
+            req[i].arrival_s = 1e-4 * (double)i;
+            req[i].n = 65536;
+            req[i].cover_off = 65536 * (i % 4);
+            req[i].msg_off = 4096 * (i % 4);
+            req[i].len = 1000;
+            req[i].k = 1;
+            req[i].op = i < 4 ? LSB_OP_EMBED : LSB_OP_EXTRACT;
+            req[i].target = i < 4 ? -1 : (int64_t)(i - 4);
+        }
+        bad += check(lsb_serve_simulate(&cfg, req, 6, res, &st, 5.0, 1000.0) == LSB_OK, "serve_simulate");
+        for (i = 0; i < 6; ++i) bad += check(res[i].status == LSB_OK, "request served");
+        bad += check(res[4].op_run == LSB_OP_EXTRACT && res[4].target == 0 && res[4].len == 1000, "extract of request 0");
+        bad += check(res[5].op_run == LSB_OP_EXTRACT && res[5].target == 1, "extract of request 1");
+        bad += check(st.launches >= 1 && st.p50_ms > 0 && st.p99_ms >= st.p50_ms, "latency figures");
+    }
+    if (bad) {
+        fprintf(stderr, "%d checks failed\n", bad);
+        return 1;
+    }
+    printf("ok\n");
+    return 0;
+}
