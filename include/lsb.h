@@ -378,7 +378,12 @@ typedef struct lsb_serve_stats {
 
 /* Serve `n_requests` requests (sorted by arrival) in real time on the
  * current device; returns when every request has completed.  results[i]
- * describes request i.  Allocates its plans, streams and events on entry and
+ * describes request i.  A request that cannot be served fails alone, its
+ * status in results[i] and counted in stats->rejected: LSB_E_CAPACITY when
+ * the request is served as an embed and its message does not fit its cover
+ * (decided at admission, nothing launched), LSB_E_NOMEM when its output can
+ * never fit the budget.  Bad fields (op, k, alignment, order) are LSB_E_ARG
+ * for the whole call.  Allocates its plans, streams and events on entry and
  * frees them on exit; never allocates device memory outside cfg->arena. */
 int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *requests, int n_requests, lsb_result *results,
               lsb_serve_stats *stats);

@@ -265,8 +265,7 @@ int check_args(const lsb_server_cfg *cfg, const lsb_request *req, int n_req, lsb
         if (i && r.arrival_s < req[i - 1].arrival_s) return fail(LSB_E_ARG, "requests must be sorted by arrival");
         if (r.target >= i) return fail(LSB_E_ARG, "request %d: target must be an earlier request", i);
         if (r.reserved) return fail(LSB_E_ARG, "request %d: reserved must be 0", i);
-        const uint64_t room = room_bytes(r.n, r.k);
-        if (room < 4 || r.len > room - 4) return fail(LSB_E_CAPACITY, "request %d: message exceeds capacity", i);
+        if (r.n > (1ull << 48)) return fail(LSB_E_ARG, "request %d: n out of range", i);
     }
     return LSB_OK;
 }
@@ -334,6 +333,19 @@ int run_scheduler(const lsb_server_cfg *cfg, const lsb_request *req, int n_req, 
                     live.pop_front();
                 }
                 if (target >= 0) sv[target].live = false;  // claimed by this extract
+            }
+            if (target < 0) {  // served as an embed: its message must fit its cover
+                const uint64_t room = room_bytes(q.n, q.k);
+                if (room < 4 || q.len > room - 4) {  // fails alone, at admission
+                    r.status = LSB_E_CAPACITY;
+                    r.op_run = LSB_OP_EMBED;
+                    r.done_s = now;
+                    ++rejected;
+                    ++finished;
+                    waiting.pop_front();
+                    progressed = true;
+                    continue;
+                }
             }
             const uint64_t need = target >= 0 ? res[target].len : q.n;
             uint64_t off = 0;

@@ -1,13 +1,13 @@
 """GPU tests of the serving loop: every request's result is the same alone
 and in the mix (tolerance 0), the HBM budget holds, and requests that can
-never fit fail alone."""
+never fit, or whose message exceeds its cover, fail alone."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 from paper_0912_0947_amd import api, serve
-from paper_0912_0947_amd._lib import E_NOMEM, OK, OP_EMBED, OP_EXTRACT
+from paper_0912_0947_amd._lib import E_CAPACITY, E_NOMEM, OK, OP_EMBED, OP_EXTRACT
 from paper_0912_0947_amd.workloads import BatchWorkload
 
 from gpu_helpers import DEV, assert_bytes_equal, to_host
@@ -109,6 +109,40 @@ def test_request_that_never_fits_fails_alone(pool):
     others = np.arange(len(req)) != big
     assert np.all(res["status"][others] == OK)
     assert stats["rejected"] == 1
+
+
+def test_oversize_message_fails_alone(pool):
+    """Embed requests whose message is one byte over their cover's capacity
+    fail with LSB_E_CAPACITY at admission; every other request of the mix is
+    served and equals its single call."""
+    wl, cover, msg = pool
+    req, ids = serve.poisson_requests(wl, 20000.0, 300, seed=651)
+    emb = np.nonzero(req["op"] == OP_EMBED)[0]
+    bad = emb[[0, 7, 8, 60]]
+    for i in bad:
+        req[i]["len"] = oracle.capacity(int(req[i]["n"]), int(req[i]["k"])) + 1
+    arena = torch.empty(int(wl.n.sum()) * 4 + (64 << 20), dtype=torch.uint8, device=DEV)
+    res, stats = serve.serve(arena, cover, msg, req, max_batch=32, n_slots=3, keep_outputs=True)
+    assert np.all(res["status"][bad] == E_CAPACITY) and stats["rejected"] == len(bad)
+    good = np.setdiff1d(np.arange(len(req)), bad)
+    assert np.all(res["status"][good] == OK)
+    # replay the served requests alone (the rejected ones launched nothing)
+    n_ok = 0
+    for i in good:
+        r = res[i]
+        if r["op_run"] == OP_EMBED:
+            c0, n, m0, ln, k = (int(req[i]["cover_off"]), int(req[i]["n"]), int(req[i]["msg_off"]),
+                                int(req[i]["len"]), int(req[i]["k"]))
+            alone = api.embed(cover[c0:c0 + n], msg[m0:m0 + ln], k)
+            o = int(r["out_off"])
+            assert torch.equal(arena[o:o + n], alone), "embed request %d differs from its single call" % i
+        else:
+            t = int(r["target"])
+            assert t not in set(bad.tolist())
+            ln, o, m0 = int(res[t]["len"]), int(r["out_off"]), int(req[t]["msg_off"])
+            assert torch.equal(arena[o:o + ln], msg[m0:m0 + ln]), "extract request %d lost the message" % i
+        n_ok += 1
+    assert n_ok == len(good)
 
 
 def inputs_rng_ints(seed, count, high):

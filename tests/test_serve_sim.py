@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from paper_0912_0947_amd import serve
-from paper_0912_0947_amd._lib import E_NOMEM, OK, OP_EMBED, OP_EXTRACT
+from paper_0912_0947_amd._lib import E_CAPACITY, E_NOMEM, OK, OP_EMBED, OP_EXTRACT
 from paper_0912_0947_amd.workloads import BatchWorkload
 
 
@@ -88,6 +88,26 @@ def test_never_fitting_request_is_rejected_alone(wl):
     assert res[big]["status"] == E_NOMEM
     assert np.all(res["status"][others] == OK)
     assert stats["rejected"] == 1
+
+
+def test_oversize_message_fails_alone(wl):
+    """Embed requests whose message exceeds their cover's capacity complete at
+    admission with LSB_E_CAPACITY; every other request is served as it would
+    be without them, and extracts never target a failed embed."""
+    req, _ = serve.poisson_requests(wl, 20000.0, 600, seed=2161, extract_frac=0.3)
+    emb = np.nonzero(req["op"] == OP_EMBED)[0]
+    bad = emb[[3, 40, 41, 200]]
+    for i in bad:
+        req[i]["len"] = oracle.capacity(int(req[i]["n"]), int(req[i]["k"])) + 1
+    res, stats = serve.simulate(req, 64 << 30, max_batch=16, n_slots=3)
+    assert np.all(res["status"][bad] == E_CAPACITY)
+    assert np.all(res["op_run"][bad] == OP_EMBED)
+    assert np.all(res["out_off"][bad] == serve.FREED)
+    good = np.setdiff1d(np.arange(len(req)), bad)
+    assert np.all(res["status"][good] == OK)
+    assert stats["rejected"] == len(bad)
+    ext = good[res["op_run"][good] == OP_EXTRACT]
+    assert not set(res["target"][ext].tolist()) & set(bad.tolist())
 
 
 def test_keep_outputs_never_frees(wl):
