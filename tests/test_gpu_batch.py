@@ -17,10 +17,10 @@ from gpu_helpers import DEV, assert_bytes_equal, to_host
 pytestmark = pytest.mark.gpu
 
 
-def _mixed_batch(count, seed, k_fixed=None, op_fixed=None):
+def _mixed_batch(count, seed, k_fixed=None, op_fixed=None, ks=None):
     """Host-side batch: per job (n, k, op, cover, payload, stego input,
     expected status/len/outputs) from the oracle.  k_fixed / op_fixed give
-    every job that k / op."""
+    every job that k / op; ks limits k to those values."""
     g = inputs.rng(seed)
     jobs = []
     for i in range(count):
@@ -33,6 +33,8 @@ def _mixed_batch(count, seed, k_fixed=None, op_fixed=None):
             n = int(g.integers(200_000, 3_000_000))
         k = int(g.integers(1, 9))
         op = OP_EMBED if g.integers(0, 2) == 0 else OP_EXTRACT
+        if ks is not None:
+            k = ks[k % len(ks)]
         k = k if k_fixed is None else k_fixed
         op = op if op_fixed is None else op_fixed
         cover = inputs.random_bytes(n, seed, i, 1)
@@ -162,6 +164,36 @@ def test_small_tiles(mixed, tv):
         _run_and_check(mixed, tile_vectors=tv)
     finally:
         batch.tune_set(old_cfg["block"], old_cfg["unroll"], old_cfg["blocks_per_cu"], old_cfg["nontemporal"], old_tv)
+
+
+@pytest.mark.parametrize("ks", [(1, 3), (2, 5, 8)])
+def test_few_class_mixed_plans(ks, restore_tiles):
+    """Jobs of 4 or 6 (op, k) classes (the kernel with every walker behind a
+    switch): every status, length and output lands at the caller's job
+    index, in shuffled orders and with 64-vector tiles; one plan then takes
+    job lists of one class (its specialised kernel), two classes and all of
+    them in turn, its graph rebuilt at each change of kernel."""
+    jobs = _mixed_batch(48, 2500 + len(ks), ks=ks)
+    assert len({(j["op"], j["k"]) for j in jobs}) == 2 * len(ks)
+    _run_and_check(jobs, order=inputs.rng(2510).permutation(len(jobs)))
+    cfg, _ = batch.tune_get()
+    batch.tune_set(cfg["block"], cfg["unroll"], cfg["blocks_per_cu"], cfg["nontemporal"], 64)
+    _run_and_check(jobs, order=inputs.rng(2511).permutation(len(jobs)))
+    # one plan, job lists of one class, two classes, then all of them (graphs rebuilt)
+    plan = batch.Plan(len(jobs))
+    try:
+        for sub in ([j for j in jobs if j["k"] == ks[0] and j["op"] == OP_EMBED],
+                    [j for j in jobs if j["k"] == ks[0]], jobs):
+            _run_and_check(sub, plan=plan)
+    finally:
+        plan.close()
+
+
+@pytest.fixture
+def restore_tiles():
+    old_cfg, old_tv = batch.tune_get()
+    yield
+    batch.tune_set(old_cfg["block"], old_cfg["unroll"], old_cfg["blocks_per_cu"], old_cfg["nontemporal"], old_tv)
 
 
 def test_plan_reuse_across_job_lists(mixed):

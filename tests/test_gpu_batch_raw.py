@@ -139,11 +139,11 @@ def test_raw_clip_uniform_plans(k, plan_op, restore_tiles):
     [(5, 8, 1, 0.5), (3, 16, 3, 1.0)],                  # tiny frames; a stream that fills its clip exactly
     [(5, 4104, 2, 0.999), (4, 100_008, 8, 0.3)],        # ragged vectors; stream ends in frame 1
     [(3, 1_000_000, 5, 0.77), (6, 4096, 4, 0.5), (2, 24, 7, 0.1)],
+    [(2, 4104, k, 0.3 + 0.08 * k) for k in range(1, 9)],  # all eight k in one plan
 ])
-def test_raw_clips_generic_kernel(specs, restore_tiles):
-    """Several clips of different k in one plan (so the generic kernel, with
-    every walker behind a switch, runs), shuffled, default and 64-vector
-    tiles."""
+def test_raw_clips_several_classes(specs, restore_tiles):
+    """Several clips of different k in one plan (the raw-capable kernel with
+    every walker behind a switch), shuffled, default and 64-vector tiles."""
     _embed_extract_clips(specs, 5200 + len(specs), batch.OP_MIXED, order_seed=5250)
     _set_tiles(64)
     _embed_extract_clips(specs, 5200 + len(specs), batch.OP_MIXED)
