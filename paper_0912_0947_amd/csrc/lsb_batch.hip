@@ -77,7 +77,7 @@ struct lsb_plan {
     bool has_extract = false;
     bool has_embed = false;
     bool has_raw = false;  // some job is a raw slice: the raw-capable kernels run
-    int cls = 0;  // 1 + 8*op + (k-1) when every job shares (op, k), else 0
+    int cls = 0;  // 1 + 8*op + (k-1) when every job shares (op, k); kClsExtractAnyK; else 0
     uint64_t total_tiles = 0;
     size_t table_bytes = 0;  // bytes of header + (max_jobs + 1) records
     size_t used_bytes = 0;   // bytes the next upload copies
@@ -328,8 +328,11 @@ int lsb_plan_update(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
     p->cls = 0;
     if (n_jobs > 0) {
         bool same = true;
+        bool same_op = true;
         for (int i = 1; i < n_jobs && same; ++i) same = d[i].op == d[0].op && d[i].k == d[0].k;
+        for (int i = 1; i < n_jobs && same_op; ++i) same_op = d[i].op == d[0].op;
         if (same) p->cls = 1 + 8 * d[0].op + (d[0].k - 1);
+        else if (same_op && d[0].op == LSB_OP_EXTRACT) p->cls = kClsExtractAnyK;
     }
     p->tile_vectors = tv;
     p->used_bytes = sizeof(PlanHeader) + sizeof(DevJob) * ((size_t)n_jobs + 1);

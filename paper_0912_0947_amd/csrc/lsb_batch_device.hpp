@@ -58,16 +58,25 @@ __device__ __forceinline__ void extract_tile(const Span &s, uint64_t v_begin, ui
     if (v_begin < v_end) extract_walk<K, UNR, NT>(s, r, v_begin, v_end, wave, n_waves, lane);
 }
 
-// CLS = 0: the tile's (op, k) is read from its job and dispatched by a switch
-// over all sixteen walkers; CLS = 1 + 8*op + (k - 1): every job of the plan
-// has that (op, k), and only its walker is compiled in.  Header and raw-slice
-// jobs share the walkers: only the span's stream fields differ.  RAW = false
-// compiles the raw-slice case out (the plan has none): the header span's
-// constant t0, header length and dword stream side then fold into the walk.
+// Job classes of a plan.  CLS = 1 + 8*op + (k - 1): every job has that
+// (op, k), and only its walker is compiled in.  CLS = 17: every job is an
+// extract, k dispatched by a switch over the eight extract walkers (61 VGPRs
+// at two vectors per lane, so two 1024-thread blocks fit a CU; the same for
+// the embed walkers needs more than the sixteen-way switch and spills).
+// CLS = 0: (op, k) read from each job, a switch over all sixteen.
+// Header and raw-slice jobs share the walkers: only the span's stream fields
+// differ.  RAW = false compiles the raw-slice case out (the plan has none):
+// the header span's constant t0, header length and dword stream side then
+// fold into the walk.
+constexpr int kClsExtractAnyK = 17, kClasses = 18;
+
 template <int UNR, bool NT, int CLS, bool RAW>
 __device__ __forceinline__ void run_tile(const DevJob &J, uint64_t v_begin, uint64_t tile_vectors,
                                          const uint8_t *cover_arena, uint8_t *stego_arena, uint8_t *msg_arena,
                                          uint32_t len, uint32_t wave, uint32_t n_waves, uint32_t lane) {
+    constexpr bool EMB = CLS == 0 || (CLS >= 1 && CLS <= 8);
+    constexpr bool EXT = CLS == 0 || CLS == kClsExtractAnyK || (CLS >= 9 && CLS <= 16);
+    constexpr int KC = CLS >= 1 && CLS <= 16 ? (CLS - 1) % 8 + 1 : 0;  // fixed k, 0: any
     Span s{};
     s.n = J.n;
     s.t0 = 0;
@@ -82,46 +91,47 @@ __device__ __forceinline__ void run_tile(const DevJob &J, uint64_t v_begin, uint
         s.hdr_len = 0;
         s.words = (((uint64_t)J.k * J.t0) & 31u) == 0;
     }
-    constexpr int OPC = CLS > 0 ? (CLS - 1) / 8 : -1;
-    if (CLS > 0 ? OPC == LSB_OP_EMBED : J.op == LSB_OP_EMBED) {
-        s.src = cover_arena + J.cover_off;
-        s.dst = stego_arena + J.stego_off;
-        s.body = msg_arena + J.msg_off;
-        s.bits = raw ? J.cap_bits : 8 * (4 + (uint64_t)J.len);
-        s.hdr = J.len;
-        if constexpr (CLS > 0) {
-            constexpr int K = (CLS - 1) % 8 + 1;
-            if constexpr (OPC == LSB_OP_EMBED) embed_tile<K, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane);
+    if constexpr (EMB) {
+        if (!EXT || J.op == LSB_OP_EMBED) {
+            s.src = cover_arena + J.cover_off;
+            s.dst = stego_arena + J.stego_off;
+            s.body = msg_arena + J.msg_off;
+            s.bits = raw ? J.cap_bits : 8 * (4 + (uint64_t)J.len);
+            s.hdr = J.len;
+            if constexpr (KC > 0) {
+                embed_tile<KC, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane);
+            } else {
+                switch (J.k) {
+                    case 1: embed_tile<1, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+                    case 2: embed_tile<2, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+                    case 3: embed_tile<3, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+                    case 4: embed_tile<4, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+                    case 5: embed_tile<5, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+                    case 6: embed_tile<6, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+                    case 7: embed_tile<7, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+                    default: embed_tile<8, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+                }
+            }
             return;
         }
-        switch (J.k) {
-            case 1: embed_tile<1, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 2: embed_tile<2, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 3: embed_tile<3, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 4: embed_tile<4, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 5: embed_tile<5, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 6: embed_tile<6, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 7: embed_tile<7, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            default: embed_tile<8, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-        }
-    } else {
+    }
+    if constexpr (EXT) {
         s.src = stego_arena + J.stego_off;
         s.out = msg_arena + J.msg_off;
         s.bits = raw ? J.cap_bits : 8 * (4 + (uint64_t)len);
-        if constexpr (CLS > 0) {
-            constexpr int K = (CLS - 1) % 8 + 1;
-            if constexpr (OPC == LSB_OP_EXTRACT) extract_tile<K, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane);
-            return;
-        }
-        switch (J.k) {
-            case 1: extract_tile<1, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 2: extract_tile<2, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 3: extract_tile<3, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 4: extract_tile<4, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 5: extract_tile<5, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 6: extract_tile<6, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            case 7: extract_tile<7, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
-            default: extract_tile<8, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+        if constexpr (KC > 0) {
+            extract_tile<KC, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane);
+        } else {
+            switch (J.k) {
+                case 1: extract_tile<1, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+                case 2: extract_tile<2, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+                case 3: extract_tile<3, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+                case 4: extract_tile<4, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+                case 5: extract_tile<5, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+                case 6: extract_tile<6, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+                case 7: extract_tile<7, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+                default: extract_tile<8, UNR, NT>(s, v_begin, tile_vectors, wave, n_waves, lane); break;
+            }
         }
     }
 }
@@ -130,12 +140,14 @@ __device__ __forceinline__ void run_tile(const DevJob &J, uint64_t v_begin, uint
 // waves on each SIMD (so at most 128 VGPRs), and anything from 4 to 7 keeps
 // one block per CU; only 8 fits two.  8 at one vector per lane (about 40
 // VGPRs) and 6 at two (75 with all sixteen walkers behind one switch); the
-// raw-capable kernels with the widest walkers (the switch, or k = 1 embed)
-// take 5 (96 VGPRs) at two vectors per lane, where 6 would spill.
+// extract-any-k class asks for 8 at two (its 61 VGPRs fit the 64 that two
+// blocks per CU leave); the raw-capable kernels with the widest walkers (the
+// switch, or k = 1 embed) take 5 (96 VGPRs) at two vectors per lane, where 6
+// would spill.
 template <int UNR, int CLS, bool RAW>
 constexpr int batch_min_waves() {
     if constexpr (UNR == 1) return 8;
-    else if constexpr (UNR == 2) return RAW && CLS <= 1 ? 5 : 6;
+    else if constexpr (UNR == 2) return CLS == kClsExtractAnyK ? 8 : (RAW && CLS <= 1 ? 5 : 6);
     else return 4;
 }
 
@@ -205,7 +217,7 @@ BatchFn batch_fn_of(int cls, std::integer_sequence<int, C...>) {
 // Kernel for a launch shape and plan class (0 = mixed jobs).
 template <bool RAW>
 BatchFn batch_fn_for(int unroll, int nt, int cls) {
-    using Classes = std::make_integer_sequence<int, 17>;
+    using Classes = std::make_integer_sequence<int, kClasses>;
     if (unroll == 1)
         return nt ? batch_fn_of<1, true, RAW>(cls, Classes{}) : batch_fn_of<1, false, RAW>(cls, Classes{});
     if (unroll == 2)

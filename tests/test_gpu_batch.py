@@ -189,6 +189,19 @@ def test_few_class_mixed_plans(ks, restore_tiles):
         plan.close()
 
 
+def test_extract_plan_of_every_k(restore_tiles):
+    """An extract-only plan whose jobs span all eight k runs the kernel with
+    the eight extract walkers behind one switch: oracle parity with corrupt
+    headers and short output buffers, shuffled, default and 64-vector tiles."""
+    jobs = _mixed_batch(64, 2600, op_fixed=OP_EXTRACT)
+    assert len({j["k"] for j in jobs}) == 8
+    assert {E_HEADER, E_BUFFER, OK} <= {j["status"] for j in jobs}
+    _run_and_check(jobs, order=inputs.rng(2601).permutation(len(jobs)))
+    cfg, _ = batch.tune_get()
+    batch.tune_set(cfg["block"], cfg["unroll"], cfg["blocks_per_cu"], cfg["nontemporal"], 64)
+    _run_and_check(jobs)
+
+
 @pytest.fixture
 def restore_tiles():
     old_cfg, old_tv = batch.tune_get()
