@@ -14,7 +14,7 @@ from ._lib import (E_ARG, OK, OP_EMBED, OP_EXTRACT, LaunchCfg, LsbError, check, 
 
 __all__ = ["capacity", "embed", "extract", "extract_sync", "embed_raw", "extract_raw",
            "paper_capacity", "paper_embed", "paper_extract", "embed_plane", "extract_plane", "sse", "psnr",
-           "video_embed_host", "verify",
+           "video_embed_host", "verify", "stream_reference",
            "tune_get", "tune_set", "autotune", "LsbError", "OK", "OP_EMBED", "OP_EXTRACT"]
 
 
