@@ -511,7 +511,8 @@ def bench_video(api, lib_handle, dev, log_fn, frames=600, h=1080, w=1920):
     device-resident per frame: 600 lsb_embed_raw launches (t0 = f * frame),
     issued from the host and, separately, captured once in a HIP graph;
     device-resident per frame, batched: the 600 frames as raw-slice jobs of
-    one batched plan (one persistent launch);
+    one batched plan (one persistent launch); extraction of the stream the
+    same three ways (whole clip, 600 raw launches, 600 batched raw jobs);
     host-streamed: the clip in pinned host memory pipelined through a 4-slot
     device ring, frames alternating over two streams that each copy in, embed
     and copy out, whose rate is bounded by PCIe, not HBM."""
@@ -590,6 +591,35 @@ def bench_video(api, lib_handle, dev, log_fn, frames=600, h=1080, w=1920):
         plan.close()
     res["device_per_frame_batched"] = {"launches": 1, "jobs": frames, "ms": round(t * 1e3, 3),
                                        "GBps": round((2 * n + ln + 4) / t / 1e9, 1)}
+    # extraction of the same stream: whole clip in one launch (header decoded
+    # on the device), 600 raw per-frame launches, 600 raw extract jobs of one
+    # plan; algorithmic bytes F + len (the F = 8 |S| carrying bytes, then the message)
+    xb = 8 * (ln + 4) + ln
+    out = torch.empty(ln, dtype=torch.uint8, device=dev)
+    ls = torch.zeros(2, dtype=torch.int32, device=dev)
+    t = timed(lambda: api.extract(stego, 1, out=out, len_status=ls))
+    assert torch.equal(out, msg) and int(ls[1]) == 0, "whole-clip extract"
+    res["device_whole_clip_extract"] = {"bytes": xb, "ms": round(t * 1e3, 3), "GBps": round(xb / t / 1e9, 1)}
+    back = torch.zeros_like(stream)
+
+    def per_frame_extract():
+        for f in range(frames):
+            api.extract_raw(stego[f * fb:(f + 1) * fb], f * fb, back, 8 * (ln + 4), 1)
+
+    t = timed(per_frame_extract)
+    assert torch.equal(back, stream), "per-frame extract"
+    res["device_per_frame_extract"] = {"launches": frames, "ms": round(t * 1e3, 3), "GBps": round(xb / t / 1e9, 1)}
+    lens = torch.zeros(frames, dtype=torch.int32, device=dev)
+    plan = batch.Plan(frames, batch.OP_EXTRACT, jobs)
+    try:
+        back.zero_()
+        t = timed(lambda: plan.extract_batch(stego, back, lens, status))
+        assert bool((status == 0).all()) and torch.equal(back, stream), "batched per-frame extract"
+    finally:
+        plan.close()
+    res["device_per_frame_batched_extract"] = {"launches": 1, "jobs": frames, "ms": round(t * 1e3, 3),
+                                               "GBps": round(xb / t / 1e9, 1)}
+    del out, back
     host = torch.empty(n, dtype=torch.uint8, pin_memory=True)
     host.copy_(clip)
     host_out = torch.empty(n, dtype=torch.uint8, pin_memory=True)
