@@ -367,7 +367,14 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
     // executable graph: rebuild it
     const BatchFn fn = batch_fn(cfg.unroll, cfg.nontemporal, p->cls, p->has_raw);
     const bool rebuild = p->exec && (cfg.block != p->cfg.block || fn != p->fn);
-    if (rebuild) destroy_graph(p);
+    if (rebuild) {
+        // the previous launch of the old graph must be finished before it goes
+        if (p->ran) {
+            const hipError_t se = hipEventSynchronize(p->done);
+            if (se != hipSuccess) return hip_fail(se, "hipEventSynchronize(plan)");
+        }
+        destroy_graph(p);
+    }
     p->cfg = cfg;
     p->fn = fn;
     const uint64_t cap_blocks = (uint64_t)(cfg.blocks_per_cu > 0 ? cfg.blocks_per_cu : 8) * (uint64_t)device_cus();
@@ -386,7 +393,12 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
     hipError_t e = hipGraphLaunch(p->exec, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     e = hipEventRecord(p->done, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "hipEventRecord(plan)");
+    if (e != hipSuccess) {
+        // without the event nothing tracks the launch: wait for it here so
+        // that a later update or destroy cannot overtake it
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        return hip_fail(e, "hipEventRecord(plan)");
+    }
     p->ran = true;
     return LSB_OK;
 }

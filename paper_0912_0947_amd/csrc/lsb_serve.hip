@@ -22,6 +22,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <chrono>
 #include <deque>
 #include <map>
@@ -111,8 +112,10 @@ class HipExecutor : public Executor {
     }
     ~HipExecutor() override {
         for (S &s : s_) {
-            // teardown: nothing useful can be done with a failure here
-            if (s.busy && s.done) (void)hipEventSynchronize(s.done);
+            // teardown: nothing useful can be done with a failure here.  A
+            // launch that failed part-way may have left work on the stream
+            // (a plan run, a status copy into status_host), so drain it first.
+            if (s.stream) (void)hipStreamSynchronize(s.stream);
             for (lsb_plan *p : s.plan)
                 if (p) lsb_plan_destroy(p);
             if (s.done) (void)hipEventDestroy(s.done);
@@ -322,11 +325,14 @@ int run_scheduler(const lsb_server_cfg *cfg, const lsb_request *req, int n_req, 
             const lsb_request &q = req[i];
             lsb_result &r = res[i];
             int target = -1;
+            size_t target_pos = 0;  // where the claimed stego sat in `live`
             if (q.op == LSB_OP_EXTRACT) {
                 if (q.target >= 0) {
                     if (sv[q.target].live) {
                         target = (int)q.target;
-                        live.erase(std::find(live.begin(), live.end(), target));
+                        const auto it = std::find(live.begin(), live.end(), target);
+                        target_pos = (size_t)(it - live.begin());
+                        live.erase(it);
                     }
                 } else if (!live.empty()) {
                     target = live.front();
@@ -359,9 +365,9 @@ int run_scheduler(const lsb_server_cfg *cfg, const lsb_request *req, int n_req, 
                 ok = arena.alloc(need, &off);
             }
             if (!ok) {
-                if (target >= 0) {  // give the claim back
+                if (target >= 0) {  // give the claim back, at its place in the age order
                     sv[target].live = true;
-                    live.push_front(target);
+                    live.insert(live.begin() + (std::ptrdiff_t)std::min(target_pos, live.size()), target);
                 }
                 if (in_flight()) {
                     if (!stalled) ++stalls;

@@ -156,3 +156,25 @@ def test_argument_errors(wl):
         serve.simulate(bad, 1 << 30)
     with pytest.raises(Exception):
         serve.simulate(req, 1 << 30, max_batch=0)
+
+
+def test_returned_claim_keeps_its_age():
+    """An extract that claims a resident stego but cannot get memory for its
+    message gives the claim back at the stego's place in the oldest-first
+    order: a later untargeted extract still reads the oldest stego."""
+    req = np.zeros(4, dtype=serve.REQ_DTYPE)
+    req["arrival_s"] = [0.0, 1e-6, 1.0, 1.0 + 1e-6]
+    req["n"] = 4096
+    req["k"] = [1, 8, 1, 1]
+    req["len"] = [100, 4000, 0, 0]
+    req["op"] = [OP_EMBED, OP_EMBED, OP_EXTRACT, OP_EXTRACT]
+    req["target"] = [-1, -1, 1, -1]
+    # 512 B of per-slot status arrays, both stegos, and a 512 B hole: the
+    # 4000-byte message of request 1 can never fit, request 0's 100 bytes can
+    budget = 512 + 2 * 4096 + 512
+    res, stats = serve.simulate(req, budget, max_batch=1, n_slots=1, keep_outputs=True)
+    assert res[0]["status"] == OK and res[1]["status"] == OK
+    assert res[2]["status"] == E_NOMEM
+    assert res[3]["status"] == OK and res[3]["op_run"] == OP_EXTRACT
+    assert res[3]["target"] == 0 and res[3]["len"] == 100
+    assert stats["rejected"] == 1
