@@ -389,11 +389,15 @@ int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *requests, int n_requ
               lsb_serve_stats *stats);
 
 /* Measurement support: the next kernel launched by an embed, extract,
- * paper-layout, plane, squared-error, verify or reference-stream call of the
- * calling thread records `start_event` and `stop_event` (hipEvent_t
+ * paper-layout, plane, squared-error, verify, reference-stream or
+ * host-streamed video call (there: the first frame's) of the calling thread
+ * records `start_event` and `stop_event` (hipEvent_t
  * handles passed as void*, created with timing enabled) at the kernel's own
  * begin and end, so that per-launch durations exclude queueing and marker
- * packets.  Applies to one launch, then clears.  Both may be NULL to clear. */
+ * packets.  Applies to the next such call only: the request clears when
+ * that call returns, also if it failed or had nothing to launch (then the
+ * events are not recorded).  lsb_autotune replaces a pending request with
+ * its own events and clears it.  Both may be NULL to clear. */
 int lsb_time_next_launch(void *start_event, void *stop_event);
 
 /* Measurement support: reference streams with the traffic mixes of the

@@ -24,6 +24,17 @@ int hip_fail(hipError_t e, const char *what);
 void take_launch_events(hipEvent_t *start, hipEvent_t *stop);
 int set_launch_events(void *start, void *stop);
 
+// Scope of an entry point that honours lsb_time_next_launch: clears the
+// error message on entry and, on return, a timing request that no launch
+// took (the call failed or had nothing to launch), so that the events never
+// reach a later call.
+struct TimedCall {
+    TimedCall() { clear_error(); }
+    ~TimedCall() { set_launch_events(nullptr, nullptr); }
+    TimedCall(const TimedCall &) = delete;
+    TimedCall &operator=(const TimedCall &) = delete;
+};
+
 // Compute units of the current device (cached per device).
 int device_cus();
 

@@ -61,7 +61,7 @@ int64_t lsb_paper_capacity(uint32_t h, uint32_t w) { return (int64_t)h * (w / 4)
 
 int lsb_paper_embed(const uint8_t *cover, uint8_t *stego, uint32_t h, uint32_t w, uint32_t c, uint32_t plane,
                     const uint8_t *data, uint64_t len, void *stream) {
-    clear_error();
+    const TimedCall timed_call;
     int rc = paper_check(h, w, c, plane, len, "lsb_paper_embed");
     if (rc) return rc;
     const uint64_t n = (uint64_t)h * w * c;
@@ -120,7 +120,7 @@ int lsb_paper_embed(const uint8_t *cover, uint8_t *stego, uint32_t h, uint32_t w
 
 int lsb_paper_extract(const uint8_t *stego, uint32_t h, uint32_t w, uint32_t c, uint32_t plane, uint8_t *data_out,
                       uint64_t len, void *stream) {
-    clear_error();
+    const TimedCall timed_call;
     int rc = paper_check(h, w, c, plane, len, "lsb_paper_extract");
     if (rc) return rc;
     if (len == 0) return LSB_OK;

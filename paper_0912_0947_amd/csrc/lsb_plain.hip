@@ -278,7 +278,7 @@ int64_t lsb_capacity(uint64_t n, int k) {
 
 int lsb_embed(const uint8_t *cover, uint8_t *stego, uint64_t n, const uint8_t *msg, uint32_t len, int k,
               void *stream) {
-    clear_error();
+    const TimedCall timed_call;
     if (k < 1 || k > 8) return fail(LSB_E_ARG, "lsb_embed: k=%d outside 1..8", k);
     const int64_t cap = lsb_capacity(n, k);
     if (cap < 0) return (int)cap;
@@ -306,7 +306,7 @@ int lsb_embed(const uint8_t *cover, uint8_t *stego, uint64_t n, const uint8_t *m
 
 int lsb_embed_raw(const uint8_t *cover, uint8_t *stego, uint64_t n, uint64_t t0, const uint8_t *stream_bytes,
                   uint64_t stream_bits, int k, void *stream) {
-    clear_error();
+    const TimedCall timed_call;
     if (k < 1 || k > 8) return fail(LSB_E_ARG, "lsb_embed_raw: k=%d outside 1..8", k);
     if (n == 0) return LSB_OK;
     if (!cover || !stego) return fail(LSB_E_ARG, "lsb_embed_raw: null cover/stego");
@@ -336,7 +336,7 @@ int lsb_embed_raw(const uint8_t *cover, uint8_t *stego, uint64_t n, uint64_t t0,
 
 int lsb_extract(const uint8_t *stego, uint64_t n, int k, uint8_t *msg_out, uint64_t out_cap, uint32_t *len_out_dev,
                 int32_t *status_out_dev, void *stream) {
-    clear_error();
+    const TimedCall timed_call;
     if (k < 1 || k > 8) return fail(LSB_E_ARG, "lsb_extract: k=%d outside 1..8", k);
     if (!len_out_dev || !status_out_dev) return fail(LSB_E_ARG, "lsb_extract: null len/status pointer");
     if (n && !stego) return fail(LSB_E_ARG, "lsb_extract: null stego");
@@ -370,7 +370,7 @@ int lsb_extract(const uint8_t *stego, uint64_t n, int k, uint8_t *msg_out, uint6
 
 int lsb_extract_raw(const uint8_t *stego, uint64_t n, uint64_t t0, uint8_t *stream_out, uint64_t stream_bits, int k,
                     void *stream) {
-    clear_error();
+    const TimedCall timed_call;
     if (k < 1 || k > 8) return fail(LSB_E_ARG, "lsb_extract_raw: k=%d outside 1..8", k);
     if (t0 > (1ull << 56) || n > (1ull << 56) || stream_bits > (1ull << 60))
         return fail(LSB_E_ARG, "lsb_extract_raw: t0/n/stream_bits out of range");

@@ -119,7 +119,7 @@ extern "C" {
 
 int lsb_embed_plane(const uint8_t *cover, uint8_t *stego, uint64_t pixels, uint32_t c, uint32_t plane,
                     const uint8_t *msg, uint32_t len, int k, void *stream) {
-    clear_error();
+    const TimedCall timed_call;
     if (k < 1 || k > 8) return fail(LSB_E_ARG, "lsb_embed_plane: k=%d outside 1..8", k);
     if (c == 0 || plane >= c) return fail(LSB_E_ARG, "lsb_embed_plane: plane %u outside 0..%u", plane, c ? c - 1 : 0);
     if (pixels > (1ull << 48)) return fail(LSB_E_ARG, "lsb_embed_plane: pixels out of range");
@@ -182,7 +182,7 @@ int lsb_embed_plane(const uint8_t *cover, uint8_t *stego, uint64_t pixels, uint3
 
 int lsb_extract_plane(const uint8_t *stego, uint64_t pixels, uint32_t c, uint32_t plane, int k, uint8_t *msg_out,
                       uint64_t out_cap, uint32_t *len_out_dev, int32_t *status_out_dev, void *stream) {
-    clear_error();
+    const TimedCall timed_call;
     if (k < 1 || k > 8) return fail(LSB_E_ARG, "lsb_extract_plane: k=%d outside 1..8", k);
     if (c == 0 || plane >= c) return fail(LSB_E_ARG, "lsb_extract_plane: plane %u outside 0..%u", plane, c ? c - 1 : 0);
     if (!len_out_dev || !status_out_dev) return fail(LSB_E_ARG, "lsb_extract_plane: null len/status pointer");
@@ -222,7 +222,7 @@ int lsb_extract_plane(const uint8_t *stego, uint64_t pixels, uint32_t c, uint32_
 }
 
 int lsb_sse(const uint8_t *a, const uint8_t *b, uint64_t n, uint64_t *sse_dev, void *stream) {
-    clear_error();
+    const TimedCall timed_call;
     if (!sse_dev) return fail(LSB_E_ARG, "lsb_sse: null result pointer");
     if (n && (!a || !b)) return fail(LSB_E_ARG, "lsb_sse: null buffer");
     if (overlaps(sse_dev, 8, a, n) || overlaps(sse_dev, 8, b, n))

@@ -112,7 +112,7 @@ using namespace lsb;
 
 extern "C" int lsb_stream_reference(int kind, int k, const uint8_t *src, uint8_t *dst, const uint8_t *side,
                                     uint64_t n, int block, int unroll, uint32_t grid, void *stream) {
-    clear_error();
+    const TimedCall timed_call;
     if (kind < LSB_REF_COPY || kind > LSB_REF_EXTRACT_MIX)
         return fail(LSB_E_ARG, "lsb_stream_reference: kind %d unknown", kind);
     if (k != 1 && k != 2 && k != 4) return fail(LSB_E_ARG, "lsb_stream_reference: k %d not 1, 2 or 4", k);

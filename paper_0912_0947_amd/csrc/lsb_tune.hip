@@ -37,7 +37,7 @@ struct Flush {
 
 extern "C" int lsb_autotune(int op, int k, uint64_t n, uint8_t *cover, uint8_t *stego, uint8_t *msg, int reps,
                             lsb_launch_cfg *best, double *best_us, void *stream_v) {
-    clear_error();
+    const TimedCall timed_call;
     if ((op != LSB_OP_EMBED && op != LSB_OP_EXTRACT) || k < 1 || k > 8 || !cover || !stego || !msg || reps < 1 ||
         reps > 1000)
         return fail(LSB_E_ARG, "lsb_autotune: bad arguments");

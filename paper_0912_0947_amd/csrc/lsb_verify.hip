@@ -103,7 +103,7 @@ using namespace lsb;
 
 extern "C" int lsb_verify(const uint8_t *cover, const uint8_t *stego, uint64_t n, const uint8_t *msg, uint32_t len,
                           int k, uint64_t *mismatches_dev, void *stream) {
-    clear_error();
+    const TimedCall timed_call;
     if (k < 1 || k > 8) return fail(LSB_E_ARG, "lsb_verify: k=%d outside 1..8", k);
     const int64_t cap = lsb_capacity(n, k);
     if (cap < 0) return (int)cap;

@@ -16,7 +16,7 @@ extern "C" int lsb_video_embed_host(const uint8_t *host_frames, uint8_t *host_st
                                     uint64_t frames, const uint8_t *stream_dev, uint64_t stream_bits, int k,
                                     uint8_t *dev_ring, uint32_t ring_slots, void *const *streams, int n_streams) {
     using namespace lsb;
-    clear_error();
+    const TimedCall timed_call;
     if (k < 1 || k > 8) return fail(LSB_E_ARG, "lsb_video_embed_host: k=%d outside 1..8", k);
     if (n_streams < 1 || n_streams > 16 || !streams)
         return fail(LSB_E_ARG, "lsb_video_embed_host: n_streams=%d outside 1..16", n_streams);
