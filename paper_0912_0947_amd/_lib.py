@@ -7,6 +7,7 @@ fallback for any operation.
 from __future__ import annotations
 
 import ctypes
+import numbers
 import os
 import threading
 
@@ -117,6 +118,29 @@ SIGNATURES = {
     "lsb_version": (ctypes.c_char_p, []),
 }
 
+def _range_checked(base, bits: int, signed: bool):
+    """An argument type that refuses integers outside ``base``'s range
+    instead of letting ctypes wrap them (a 2**32 + 5 byte length would
+    otherwise reach the library as 5)."""
+    lo, hi = (-(1 << (bits - 1)), (1 << (bits - 1)) - 1) if signed else (0, (1 << bits) - 1)
+
+    class Checked(base):
+        @classmethod
+        def from_param(cls, v):
+            if isinstance(v, numbers.Integral) and not isinstance(v, bool):
+                v = int(v)
+                if not lo <= v <= hi:
+                    raise OverflowError("%d is outside the range of %s" % (v, base.__name__))
+                return base(v)
+            return base.from_param(v)
+
+    Checked.__name__ = base.__name__
+    return Checked
+
+
+_CHECKED = {_U64: _range_checked(_U64, 64, False), _I64: _range_checked(_I64, 64, True),
+            _U32: _range_checked(_U32, 32, False), _I: _range_checked(_I, 32, True)}
+
 _lock = threading.Lock()
 _lib = None
 
@@ -141,7 +165,7 @@ def lib():
                 for name, (res, args) in SIGNATURES.items():
                     fn = getattr(handle, name)
                     fn.restype = res
-                    fn.argtypes = args
+                    fn.argtypes = [_CHECKED.get(a, a) for a in args]
                 from . import tune
                 tune.load(handle)  # stored launch configurations, if any
                 _lib = handle

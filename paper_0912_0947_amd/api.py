@@ -31,6 +31,10 @@ def _u8(t: torch.Tensor, name: str) -> int:
         raise TypeError("%s must live on a GPU (no CPU path exists)" % name)
     if not t.is_contiguous():
         raise TypeError("%s must be contiguous" % name)
+    if t.device.index != torch.cuda.current_device():
+        # the library launches on the current device
+        raise ValueError("%s is on %s but the current device is cuda:%d (use torch.cuda.device)"
+                         % (name, t.device, torch.cuda.current_device()))
     return t.data_ptr() if t.numel() else 0
 
 

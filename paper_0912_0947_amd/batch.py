@@ -25,17 +25,67 @@ def make_jobs(count: int) -> np.ndarray:
     return np.zeros(count, dtype=JOB_DTYPE)
 
 
-def _ptr(t):
+def _extents(jobs: np.ndarray, op_mode: int) -> tuple[int, int, int]:
+    """Bytes that the cover, stego and message arenas must hold for ``jobs``:
+    one past the furthest byte that any job reads or writes in each."""
+    if not jobs.size:
+        return 0, 0, 0
+    if max(int(jobs[f].max()) for f in ("cover_off", "stego_off", "msg_off")) >= 1 << 62:
+        raise ValueError("a job offset lies beyond any device arena")
+    op = jobs["op"] if op_mode == OP_MIXED else np.full(jobs.size, op_mode, np.uint8)
+    raw = (jobs["flags"] & JOB_RAW) != 0
+    n, k = jobs["n"], jobs["k"].astype(np.uint64)
+    # raw slices: stream bytes [k*t0/8, ceil(min(k*(t0+n), stream_bits)/8)) of the stream at msg_off
+    begin = k * jobs["t0"]
+    end = np.minimum(k * (jobs["t0"] + n), jobs["stream_bits"])
+    raw_bytes = np.where(end > begin, (end + 7) // 8, 0)
+    # header jobs: at most the message capacity of the cover
+    room = n * k // 8
+    cap = np.minimum(np.where(room >= 4, room - 4, 0), 0xFFFFFFFF)
+    ln = jobs["len"].astype(np.uint64)
+    header_bytes = np.where(op == OP_EMBED, np.where(ln <= cap, ln, 0), np.minimum(jobs["msg_cap"], cap))
+    msg_bytes = np.where(raw, raw_bytes, header_bytes)
+    busy = n > 0
+    emb = busy & (op == OP_EMBED)
+
+    def reach(off, size, mask):
+        return int((off + size)[mask].max()) if mask.any() else 0
+
+    return (reach(jobs["cover_off"], n, emb), reach(jobs["stego_off"], n, busy),
+            reach(jobs["msg_off"], msg_bytes, msg_bytes > 0))
+
+
+def _ptr(t, name: str, need: int = 0, dtypes=(torch.uint8,)):
+    """Device pointer of ``t`` after checking it: dtype, contiguous, on the
+    current device, and at least ``need`` elements.  None passes as NULL
+    when nothing is needed from it."""
     if t is None:
+        if need:
+            raise ValueError("%s is required by the plan's jobs" % name)
         return None
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError("arenas and status buffers must be device tensors")
+        raise TypeError("%s must be a device tensor" % name)
+    if t.dtype not in dtypes:
+        raise TypeError("%s must be of dtype %s" % (name, " or ".join(str(d) for d in dtypes)))
+    if not t.is_contiguous():
+        raise TypeError("%s must be contiguous" % name)
+    if t.device.index != torch.cuda.current_device():
+        raise ValueError("%s is on %s but the current device is cuda:%d" % (name, t.device,
+                                                                            torch.cuda.current_device()))
+    if t.numel() < need:
+        raise ValueError("%s holds %d elements; the plan's jobs need %d" % (name, t.numel(), need))
     return ctypes.c_void_p(t.data_ptr())
+
+
+_WORD = (torch.int32, torch.uint32) if hasattr(torch, "uint32") else (torch.int32,)
 
 
 class Plan:
     """Owns an lsb_plan: a device job table, its pinned host mirror and the
-    HIP graph {table upload, prologue, persistent kernel}."""
+    HIP graph {table upload, prologue, persistent kernel}.  Before each run
+    the binding checks that the arenas hold every byte the jobs name and
+    that the status and length arrays have an entry per job (the C call
+    takes base pointers only and trusts the caller on this)."""
 
     def __init__(self, max_jobs: int, op: int = OP_MIXED, jobs: np.ndarray | None = None):
         """Room for ``max_jobs`` jobs; ``op`` = OP_EMBED / OP_EXTRACT makes
@@ -50,14 +100,22 @@ class Plan:
             ptr = jobs.ctypes.data_as(ctypes.POINTER(Job))
         check(lib().lsb_plan_create(ctypes.byref(self._p), ptr, int(max_jobs), int(op)))
         self.max_jobs = int(max_jobs)
-        self.n_jobs = int(max_jobs) if jobs is not None else 0
+        self.op = int(op)
+        self.n_jobs = 0
+        self._need = (0, 0, 0)
+        if jobs is not None:
+            self._installed(jobs)
+
+    def _installed(self, jobs: np.ndarray) -> None:
+        self.n_jobs = int(jobs.size)
+        self._need = _extents(jobs, self.op)
 
     def set_jobs(self, jobs: np.ndarray) -> None:
         """Replace the job list (lsb_plan_update)."""
         jobs = np.ascontiguousarray(jobs, dtype=JOB_DTYPE)
         ptr = jobs.ctypes.data_as(ctypes.POINTER(Job)) if jobs.size else None
         check(lib().lsb_plan_update(self._p, ptr, int(jobs.size)))
-        self.n_jobs = int(jobs.size)
+        self._installed(jobs)
 
     update = set_jobs
 
@@ -65,15 +123,20 @@ class Plan:
         """lsb_embed_batch: every job of the plan must be an embed."""
         if stream is None:
             stream = torch.cuda.current_stream()
-        check(lib().lsb_embed_batch(self._p, _ptr(cover_arena), _ptr(stego_arena), _ptr(msg_arena),
-                                    _ptr(status_dev), ctypes.c_void_p(stream.cuda_stream)))
+        c, st, m = self._need
+        check(lib().lsb_embed_batch(self._p, _ptr(cover_arena, "cover_arena", c), _ptr(stego_arena, "stego_arena", st),
+                                    _ptr(msg_arena, "msg_arena", m), _ptr(status_dev, "status_dev", self.n_jobs, _WORD),
+                                    ctypes.c_void_p(stream.cuda_stream)))
 
     def extract_batch(self, stego_arena, msg_arena, len_dev, status_dev, stream=None) -> None:
         """lsb_extract_batch: every job of the plan must be an extract."""
         if stream is None:
             stream = torch.cuda.current_stream()
-        check(lib().lsb_extract_batch(self._p, _ptr(stego_arena), _ptr(msg_arena), _ptr(len_dev),
-                                      _ptr(status_dev), ctypes.c_void_p(stream.cuda_stream)))
+        _, st, m = self._need
+        check(lib().lsb_extract_batch(self._p, _ptr(stego_arena, "stego_arena", st), _ptr(msg_arena, "msg_arena", m),
+                                      _ptr(len_dev, "len_dev", self.n_jobs, _WORD),
+                                      _ptr(status_dev, "status_dev", self.n_jobs, _WORD),
+                                      ctypes.c_void_p(stream.cuda_stream)))
 
     @property
     def tiles(self) -> int:
@@ -82,8 +145,12 @@ class Plan:
     def run(self, cover_arena, stego_arena, msg_arena, len_dev, status_dev, stream=None) -> None:
         if stream is None:
             stream = torch.cuda.current_stream()
-        check(lib().lsb_plan_run(self._p, _ptr(cover_arena), _ptr(stego_arena), _ptr(msg_arena),
-                                 _ptr(len_dev), _ptr(status_dev), ctypes.c_void_p(stream.cuda_stream)))
+        c, st, m = self._need
+        check(lib().lsb_plan_run(self._p, _ptr(cover_arena, "cover_arena", c), _ptr(stego_arena, "stego_arena", st),
+                                 _ptr(msg_arena, "msg_arena", m),
+                                 _ptr(len_dev, "len_dev", self.n_jobs if len_dev is not None else 0, _WORD),
+                                 _ptr(status_dev, "status_dev", self.n_jobs, _WORD),
+                                 ctypes.c_void_p(stream.cuda_stream)))
 
     def close(self) -> None:
         if self._p:

@@ -45,6 +45,21 @@ def serve(arena: torch.Tensor, cover_pool: torch.Tensor, msg_pool: torch.Tensor,
     Returns (results structured array, stats dict)."""
     requests = np.ascontiguousarray(requests, dtype=REQ_DTYPE)
     results = np.zeros(requests.size, dtype=RES_DTYPE)
+    for name, t in (("arena", arena), ("cover_pool", cover_pool), ("msg_pool", msg_pool)):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.uint8 or not t.is_contiguous():
+            raise TypeError("%s must be a contiguous torch.uint8 device tensor" % name)
+        if t.device.index != torch.cuda.current_device():
+            raise ValueError("%s is on %s but the current device is cuda:%d" % (name, t.device,
+                                                                                torch.cuda.current_device()))
+    # any request may run as an embed (an extract with nothing resident does),
+    # so every request's cover and message must lie inside the pools
+    if requests.size:
+        if int((requests["cover_off"] + requests["n"]).max()) > cover_pool.numel() or \
+                max(int(requests["cover_off"].max()), int(requests["n"].max())) >= 1 << 62:
+            raise ValueError("a request's cover lies outside cover_pool")
+        if int((requests["msg_off"] + requests["len"]).max()) > msg_pool.numel() or \
+                int(requests["msg_off"].max()) >= 1 << 62:
+            raise ValueError("a request's message lies outside msg_pool")
     cfg = ServerCfg(arena.data_ptr(), arena.numel(), cover_pool.data_ptr(), msg_pool.data_ptr(),
                     int(max_batch), int(n_slots), int(bool(keep_outputs)), 0)
     stats = ServeStats()

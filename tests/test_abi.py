@@ -89,3 +89,17 @@ def test_no_cpu_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         _lib.lib()
+
+
+def test_binding_refuses_integers_that_would_wrap(lib):
+    """ctypes would pass 2**32 + 5 to a uint32 parameter as 5; the binding
+    refuses any integer outside its parameter's range instead."""
+    assert lib.lsb_capacity(786432, 1) == 98300
+    import numpy as np
+    assert lib.lsb_capacity(np.uint64(786432), np.int64(1)) == 98300
+    for args in [(786432, 2**32 + 1), (-1, 1), (2**64, 1)]:
+        with pytest.raises(ctypes.ArgumentError):
+            lib.lsb_capacity(*args)
+    assert lib.lsb_paper_capacity(7, 1024) == 7 * 256
+    with pytest.raises(ctypes.ArgumentError):
+        lib.lsb_paper_capacity(2**32 + 7, 1024)

@@ -361,3 +361,39 @@ def test_in_place_and_empty_plans():
             assert torch.equal(buf[o:o + n], stego[o:o + n]), "job %d in place" % i
     finally:
         plan.close()
+
+
+def test_binding_refuses_buffers_the_jobs_do_not_fit():
+    """The C call takes arena base pointers only; the binding checks, before
+    anything is enqueued, that every arena holds the bytes its jobs name and
+    that the status and length arrays have an entry per job."""
+    wl = BatchWorkload(8, oracle.capacity, seed=441, lo=64, hi=600)
+    cover, stego, msg, out = wl.allocate(DEV)
+    status = torch.full((wl.count,), 99, dtype=torch.int32, device=DEV)
+    lens = torch.zeros(wl.count, dtype=torch.int32, device=DEV)
+    jobs = wl.jobs(OP_EMBED)
+    need_c = int((jobs["cover_off"] + jobs["n"]).max())
+    need_m = int((jobs["msg_off"] + jobs["len"]).max())
+    pe, px = batch.Plan(wl.count, OP_EMBED, jobs), batch.Plan(wl.count, OP_EXTRACT, wl.jobs(OP_EXTRACT))
+    try:
+        bad = [
+            (ValueError, lambda: pe.embed_batch(cover[:need_c - 1], stego, msg, status)),
+            (ValueError, lambda: pe.embed_batch(cover, stego[:need_c - 1], msg, status)),
+            (ValueError, lambda: pe.embed_batch(cover, stego, msg[:need_m - 1], status)),
+            (ValueError, lambda: pe.embed_batch(cover, stego, msg, status[:-1])),
+            (TypeError, lambda: pe.embed_batch(cover, stego, msg, status.to(torch.uint8))),
+            (TypeError, lambda: pe.embed_batch(cover.view(torch.int8), stego, msg, status)),
+            (ValueError, lambda: px.extract_batch(stego, out, lens[:-1], status)),
+            (ValueError, lambda: px.extract_batch(stego, out, None, status)),
+        ]
+        for exc, call in bad:
+            with pytest.raises(exc):
+                call()
+        torch.cuda.synchronize()
+        assert bool((status == 99).all()), "a refused call ran"
+        pe.embed_batch(cover[:need_c], stego, msg[:need_m], status)  # exactly enough
+        torch.cuda.synchronize()
+        assert bool((status == OK).all())
+    finally:
+        pe.close()
+        px.close()

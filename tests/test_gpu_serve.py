@@ -148,3 +148,23 @@ def test_oversize_message_fails_alone(pool):
 def inputs_rng_ints(seed, count, high):
     from paper_0912_0947_amd import inputs
     return inputs.rng(seed).integers(0, high, size=count)
+
+
+def test_binding_refuses_requests_outside_the_pools(pool):
+    """The C call takes pool base pointers only; the binding checks first
+    that every request's cover and message lie inside the pools (any
+    request may run as an embed) and that the buffers are uint8 device
+    tensors."""
+    wl, cover, msg = pool
+    req, _ = serve.poisson_requests(wl, 10000.0, 20, seed=671)
+    arena = torch.empty(1 << 24, dtype=torch.uint8, device=DEV)
+    need_c = int((req["cover_off"] + req["n"]).max())
+    need_m = int((req["msg_off"] + req["len"]).max())
+    with pytest.raises(ValueError):
+        serve.serve(arena, cover[:need_c - 1], msg, req, max_batch=8, n_slots=2)
+    with pytest.raises(ValueError):
+        serve.serve(arena, cover, msg[:need_m - 1], req, max_batch=8, n_slots=2)
+    with pytest.raises(TypeError):
+        serve.serve(arena.view(torch.int8), cover, msg, req, max_batch=8, n_slots=2)
+    res, stats = serve.serve(arena, cover[:need_c], msg[:need_m], req, max_batch=8, n_slots=2)
+    assert np.all(res["status"] == OK)
