@@ -130,7 +130,8 @@ int lsb_extract_raw(const uint8_t *stego, uint64_t n, uint64_t t0,
  * lsb_paper_capacity: h * floor(w/4) bytes.  Host-only.
  * lsb_paper_embed: stego = cover with the data placed as above; every other
  *   byte copied (stego == cover: in place).  LSB_E_CAPACITY if len exceeds
- *   the capacity, LSB_E_ARG if plane >= c or buffers overlap otherwise.
+ *   the capacity, LSB_E_ARG if plane >= c, h*w*c > 2^48 or buffers overlap
+ *   otherwise.
  * lsb_paper_extract: data_out[0..len) from the stego image (data_out's
  *   bytes are all written).
  */
@@ -148,7 +149,8 @@ int lsb_paper_extract(const uint8_t *stego, uint32_t h, uint32_t w,
  * the bytes p*c + plane of an HWC image of `pixels` pixels, in raster order;
  * stream, header, bit order and errors as lsb_embed / lsb_extract, with the
  * capacity lsb_capacity(pixels, k).  lsb_embed_plane copies the other bytes
- * (stego == cover: in place, only plane bytes are rewritten).
+ * (stego == cover: in place, only plane bytes are rewritten).  LSB_E_ARG
+ * also for plane >= c, pixels > 2^48 or c > 65536.
  */
 int lsb_embed_plane(const uint8_t *cover, uint8_t *stego, uint64_t pixels,
                     uint32_t c, uint32_t plane, const uint8_t *msg,

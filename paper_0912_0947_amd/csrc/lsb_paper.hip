@@ -48,6 +48,7 @@ static_assert(paper_row_lds_bytes(kPaperRowChunkMax) <= 64 * 1024, "row kernel L
 
 static int paper_check(uint32_t h, uint32_t w, uint32_t c, uint32_t plane, uint64_t len, const char *who) {
     if (c == 0 || plane >= c) return fail(LSB_E_ARG, "%s: plane %u outside 0..%u", who, plane, c ? c - 1 : 0);
+    if ((uint64_t)h * w > (1ull << 48) / c) return fail(LSB_E_ARG, "%s: h*w*c above 2^48 bytes", who);
     const uint64_t cap = (uint64_t)h * (w / 4);
     if (len > cap)
         return fail(LSB_E_CAPACITY, "%s: %llu data bytes exceed the capacity h*floor(w/4) = %llu", who,

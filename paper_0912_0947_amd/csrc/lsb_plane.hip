@@ -122,7 +122,7 @@ int lsb_embed_plane(const uint8_t *cover, uint8_t *stego, uint64_t pixels, uint3
     const TimedCall timed_call;
     if (k < 1 || k > 8) return fail(LSB_E_ARG, "lsb_embed_plane: k=%d outside 1..8", k);
     if (c == 0 || plane >= c) return fail(LSB_E_ARG, "lsb_embed_plane: plane %u outside 0..%u", plane, c ? c - 1 : 0);
-    if (pixels > (1ull << 48)) return fail(LSB_E_ARG, "lsb_embed_plane: pixels out of range");
+    if (pixels > (1ull << 48) || c > 65536) return fail(LSB_E_ARG, "lsb_embed_plane: pixels or channels out of range");
     const int64_t cap = lsb_capacity(pixels, k);
     if (cap < 0) return (int)cap;
     if ((uint64_t)len > (uint64_t)cap)
@@ -188,12 +188,16 @@ int lsb_extract_plane(const uint8_t *stego, uint64_t pixels, uint32_t c, uint32_
     if (!len_out_dev || !status_out_dev) return fail(LSB_E_ARG, "lsb_extract_plane: null len/status pointer");
     if (pixels && !stego) return fail(LSB_E_ARG, "lsb_extract_plane: null stego");
     if (out_cap && !msg_out) return fail(LSB_E_ARG, "lsb_extract_plane: null msg_out with out_cap > 0");
-    if (pixels > (1ull << 48)) return fail(LSB_E_ARG, "lsb_extract_plane: pixels out of range");
+    if (pixels > (1ull << 48) || c > 65536)
+        return fail(LSB_E_ARG, "lsb_extract_plane: pixels or channels out of range");
     const uint64_t n = pixels * c;
     const uint64_t room = room_bytes(pixels, k);
     const uint64_t cap = room >= 4 ? room - 4 : 0;
     const uint64_t max_len = out_cap < cap ? out_cap : cap;
     if (overlaps(msg_out, max_len, stego, n)) return fail(LSB_E_ARG, "lsb_extract_plane: msg_out overlaps stego");
+    if (overlaps(len_out_dev, 4, stego, n) || overlaps(status_out_dev, 4, stego, n) ||
+        overlaps(len_out_dev, 4, msg_out, max_len) || overlaps(status_out_dev, 4, msg_out, max_len))
+        return fail(LSB_E_ARG, "lsb_extract_plane: len/status overlap a data buffer");
     if (c == 1) return lsb_extract(stego, pixels, k, msg_out, out_cap, len_out_dev, status_out_dev, stream);
     Span s{};
     s.src = stego;

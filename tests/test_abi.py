@@ -103,3 +103,15 @@ def test_binding_refuses_integers_that_would_wrap(lib):
     assert lib.lsb_paper_capacity(7, 1024) == 7 * 256
     with pytest.raises(ctypes.ArgumentError):
         lib.lsb_paper_capacity(2**32 + 7, 1024)
+
+
+def test_image_sizes_that_would_overflow_are_refused(lib):
+    """h*w*c and pixels*c are formed in 64 bits; sizes past the stated
+    limits are LSB_E_ARG before anything else is looked at (no GPU call)."""
+    E_ARG = -1
+    # 2^31 x 2^31 x 2^16 wraps to 0 in 64 bits: refused, not taken as empty
+    assert lib.lsb_paper_embed(None, None, 2**31, 2**31, 2**16, 0, None, 0, None) == E_ARG
+    assert lib.lsb_paper_extract(None, 2**31, 2**31, 2**16, 0, None, 1, None) == E_ARG
+    assert b"2^48" in lib.lsb_last_error()
+    assert lib.lsb_embed_plane(None, None, 16, 65537, 0, None, 0, 1, None) == E_ARG
+    assert lib.lsb_embed_plane(None, None, 2**48 + 1, 3, 0, None, 0, 1, None) == E_ARG
