@@ -1,0 +1,125 @@
+"""Calls from several host threads at once, each on its own stream, and
+header embed/extract captured in a HIP graph.
+
+Threads: every thread's results match the oracle byte for byte while other
+threads launch, install launch shapes in the tuning table and fail calls of
+their own; each thread's lsb_last_error is its own.  Graph: every replay,
+with new cover and message bytes copied in eagerly between replays, gives
+the oracle's stego, message, length and status."""
+import threading
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_0912_0947_amd import api, inputs
+from paper_0912_0947_amd._lib import OK, OP_EMBED, OP_EXTRACT, lib
+
+from gpu_helpers import DEV, assert_bytes_equal, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(t, k):
+    n = (1 << 20) + 4099 * t + 13 * k
+    cover = inputs.random_bytes(n, 3401, t, k)
+    msg = inputs.random_bytes(oracle.capacity(n, k) - 7 * t, 3402, t, k)
+    rc, want = oracle.embed(cover, msg, k)
+    assert rc == OK
+    return cover, msg, want
+
+
+def test_threads_on_their_own_streams():
+    threads, ks = 4, (1, 2, 3, 4, 5, 6, 7, 8)
+    cases = {(t, k): _case(t, k) for t in range(threads) for k in ks}
+    failures = []
+    start = threading.Barrier(threads + 1)
+
+    def worker(t):
+        try:
+            stream = torch.cuda.Stream()  # default priority
+            start.wait()
+            with torch.cuda.stream(stream):
+                for rep in range(2):
+                    for k in ks:
+                        cover, msg, want = cases[(t, k)]
+                        stego = api.embed(torch.from_numpy(cover).to(DEV, non_blocking=False),
+                                          torch.from_numpy(msg).to(DEV), k)
+                        out, ls = api.extract(stego, k)
+                        stream.synchronize()
+                        assert np.array_equal(stego.cpu().numpy(), want), "thread %d k=%d embed" % (t, k)
+                        lsn = ls.cpu().numpy()
+                        assert lsn[1] == OK and int(np.uint32(lsn[0])) == msg.size, "thread %d k=%d" % (t, k)
+                        assert np.array_equal(out.cpu().numpy()[:msg.size], msg), "thread %d k=%d extract" % (t, k)
+                        if t == 0:  # a failing call: its message stays on this thread
+                            with pytest.raises(Exception):
+                                api.embed(stego, torch.zeros(8, dtype=torch.uint8, device=DEV), 9)
+                            assert b"k=9" in lib().lsb_last_error()
+                        else:
+                            assert lib().lsb_last_error() == b"", "thread %d sees an error" % t
+                        if t == 1:  # reinstall a launch shape while the others launch
+                            for op in (OP_EMBED, OP_EXTRACT):
+                                cfg = api.tune_get(op, k, cover.size)
+                                api.tune_set(op, k, 20, cfg["block"], cfg["unroll"], cfg["blocks_per_cu"],
+                                             cfg["nontemporal"], cfg["pack"])
+        except BaseException as e:  # reported by the main thread
+            failures.append((t, repr(e)))
+            try:
+                start.abort()
+            except Exception:
+                pass
+
+    ts = [threading.Thread(target=worker, args=(t,)) for t in range(threads)]
+    for th in ts:
+        th.start()
+    try:
+        start.wait(timeout=60)
+    except threading.BrokenBarrierError:
+        pass
+    for th in ts:
+        th.join(timeout=120)
+        assert not th.is_alive(), "a worker thread did not finish"
+    torch.cuda.synchronize()
+    assert not failures, failures
+
+
+@pytest.mark.parametrize("k", [1, 3, 4])
+def test_header_calls_in_a_graph(k):
+    n = 3 * 65536 + 77
+    ln = oracle.capacity(n, k) - 5
+    cover_s = torch.empty(n, dtype=torch.uint8, device=DEV)
+    msg_s = torch.empty(ln, dtype=torch.uint8, device=DEV)
+    stego_s = torch.empty(n, dtype=torch.uint8, device=DEV)
+    out_s = torch.empty(ln + 64, dtype=torch.uint8, device=DEV)
+    ls_s = torch.empty(2, dtype=torch.int32, device=DEV)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # one eager pass before capture
+        api.embed(cover_s, msg_s, k, out=stego_s)
+        api.extract(stego_s, k, out=out_s, len_status=ls_s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        api.embed(cover_s, msg_s, k, out=stego_s)
+        api.extract(stego_s, k, out=out_s, len_status=ls_s)
+    for rep in range(3):
+        cover = inputs.random_bytes(n, 3403, k, rep)
+        msg = inputs.random_bytes(ln, 3404, k, rep)
+        rc, want = oracle.embed(cover, msg, k)
+        assert rc == OK
+        cover_s.copy_(torch.from_numpy(cover))  # eager work between replays
+        msg_s.copy_(torch.from_numpy(msg))
+        out_s.fill_(0xA5)
+        ls_s.fill_(-99)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        tag = "graph replay %d, k=%d" % (rep, k)
+        assert_bytes_equal(to_host(stego_s), want, tag + " stego")
+        lsn = ls_s.cpu().numpy()
+        assert lsn[1] == OK and lsn[0] == ln, tag + " len/status %s" % lsn
+        got = to_host(out_s)
+        assert_bytes_equal(got[:ln], msg, tag + " message")
+        assert np.all(got[ln:] == 0xA5), tag + " bytes past the message"
+    del g

@@ -178,3 +178,38 @@ def test_returned_claim_keeps_its_age():
     assert res[3]["status"] == OK and res[3]["op_run"] == OP_EXTRACT
     assert res[3]["target"] == 0 and res[3]["len"] == 100
     assert stats["rejected"] == 1
+
+
+def test_concurrent_simulations_match_serial(wl):
+    """The scheduler keeps no shared state: four host threads simulating at
+    once get the serial results, and a failing call on one thread leaves
+    its error message on that thread only."""
+    import threading
+
+    from paper_0912_0947_amd._lib import lib
+
+    reqs = [serve.poisson_requests(wl, 20000.0, 1500, seed=2190 + t)[0] for t in range(4)]
+    serial = [serve.simulate(r, 1 << 30, max_batch=16, n_slots=3) for r in reqs]
+    got, errors = [None] * 4, []
+
+    def run(t):
+        try:
+            for _ in range(3):
+                got[t] = serve.simulate(reqs[t], 1 << 30, max_batch=16, n_slots=3)
+                if t == 0:
+                    with pytest.raises(Exception):
+                        serve.simulate(reqs[t], 1 << 30, max_batch=0)
+                    assert b"max_batch" in lib().lsb_last_error()
+                else:
+                    assert lib().lsb_last_error() == b""
+        except BaseException as e:
+            errors.append((t, repr(e)))
+
+    ts = [threading.Thread(target=run, args=(t,)) for t in range(4)]
+    for th in ts:
+        th.start()
+    for th in ts:
+        th.join(timeout=120)
+    assert not errors, errors
+    for (a, sa), (b, sb) in zip(serial, got):
+        assert np.array_equal(a, b) and sa == sb
