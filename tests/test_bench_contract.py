@@ -60,3 +60,19 @@ def test_threaded_oracle_leg():
             for k in bench.KS}
     r = bench.cpu_baseline_threads(cover, msgs, 5)
     assert r["kind"] == "oracle" and r["cores"] == 5 and r["value"] > 0 and r["unit"] == "GB/s"
+
+
+def test_single_thread_oracle_leg_repeats_to_its_time_floor():
+    """The single-thread baseline repeats whole steps until its time floor
+    (at least one step, at most max_steps) and counts the bytes of each."""
+    import numpy as np
+
+    import oracle
+
+    cover = (np.arange(4096, dtype=np.uint32) * 37 % 251).astype(np.uint8)
+    msgs = {k: np.full(oracle.capacity(cover.size, k), 0x5A, np.uint8) for k in bench.KS}
+    one = bench.cpu_baseline(cover, msgs, min_seconds=0.0)
+    assert one["sample"].startswith("1 full step:") and one["cores"] == 1
+    many = bench.cpu_baseline(cover, msgs, min_seconds=1e9, max_steps=3)
+    assert many["sample"].startswith("3 full steps:")
+    assert one["value"] > 0 and many["value"] > 0
