@@ -38,6 +38,36 @@ def _u8(t: torch.Tensor, name: str) -> int:
     return t.data_ptr() if t.numel() else 0
 
 
+def _len_status_ptr(t: torch.Tensor) -> int:
+    """Device address of a [length, status] pair: two int32 words that the
+    kernel writes."""
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int32 or t.numel() < 2 or not t.is_cuda \
+            or not t.is_contiguous():
+        raise TypeError("len_status must be a contiguous int32 device tensor of 2 elements")
+    if t.device.index != torch.cuda.current_device():
+        raise ValueError("len_status is on %s but the current device is cuda:%d" % (t.device,
+                                                                                   torch.cuda.current_device()))
+    return t.data_ptr()
+
+
+def _word64_ptr(t: torch.Tensor, name: str) -> ctypes.c_void_p:
+    """Device address of one 64-bit result word that a kernel writes."""
+    if not isinstance(t, torch.Tensor) or t.dtype not in (torch.int64, torch.uint64) or t.numel() < 1 \
+            or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous 64-bit integer device tensor of at least 1 element" % name)
+    if t.device.index != torch.cuda.current_device():
+        raise ValueError("%s is on %s but the current device is cuda:%d" % (name, t.device,
+                                                                           torch.cuda.current_device()))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _slice_stream_end(k: int, t0: int, n: int, stream_bits: int) -> int:
+    """One past the last stream byte that cover bytes [t0, t0 + n) touch:
+    ceil(min(k*(t0 + n), stream_bits) / 8), or 0 when they carry no bit."""
+    end = min(k * (t0 + n), stream_bits)
+    return -(-end // 8) if end > k * t0 else 0
+
+
 def capacity(n: int, k: int) -> int:
     """Message capacity in bytes of an n-byte cover at k bits per byte."""
     return check(lib().lsb_capacity(n, k))
@@ -65,9 +95,7 @@ def extract(stego: torch.Tensor, k: int, out: torch.Tensor | None = None,
         out = torch.empty(max(int(cap), 0), dtype=torch.uint8, device=stego.device)
     if len_status is None:
         len_status = torch.empty(2, dtype=torch.int32, device=stego.device)
-    if len_status.dtype != torch.int32 or len_status.numel() < 2 or not len_status.is_cuda:
-        raise TypeError("len_status must be an int32 device tensor of 2 elements")
-    base = len_status.data_ptr()
+    base = _len_status_ptr(len_status)
     check(lib().lsb_extract(_u8(stego, "stego"), stego.numel(), k,
                             _u8(out, "out") if out.numel() else None, out.numel(),
                             ctypes.c_void_p(base), ctypes.c_void_p(base + 4), _stream_ptr(stream)))
@@ -94,6 +122,9 @@ def embed_raw(cover: torch.Tensor, t0: int, stream_bytes: torch.Tensor, stream_b
     stego = torch.empty_like(cover) if out is None else out
     if stego.numel() != cover.numel():
         raise ValueError("out must have as many bytes as cover")
+    if 1 <= k <= 8 and stream_bytes.numel() < _slice_stream_end(k, t0, cover.numel(), stream_bits):
+        raise ValueError("stream_bytes holds %d bytes; the slice reads up to byte %d"
+                         % (stream_bytes.numel(), _slice_stream_end(k, t0, cover.numel(), stream_bits)))
     check(lib().lsb_embed_raw(_u8(cover, "cover"), _u8(stego, "out"), cover.numel(), t0,
                               _u8(stream_bytes, "stream_bytes"), stream_bits, k, _stream_ptr(stream)))
     return stego
@@ -103,6 +134,9 @@ def extract_raw(stego: torch.Tensor, t0: int, stream_out: torch.Tensor, stream_b
                 stream=None) -> torch.Tensor:
     """Extract the stream bits carried by cover bytes [t0, t0+n) into the
     logical-stream buffer ``stream_out``."""
+    if 1 <= k <= 8 and stream_out.numel() < _slice_stream_end(k, t0, stego.numel(), stream_bits):
+        raise ValueError("stream_out holds %d bytes; the slice writes up to byte %d"
+                         % (stream_out.numel(), _slice_stream_end(k, t0, stego.numel(), stream_bits)))
     check(lib().lsb_extract_raw(_u8(stego, "stego"), stego.numel(), t0, _u8(stream_out, "stream_out"),
                                 stream_bits, k, _stream_ptr(stream)))
     return stream_out
@@ -132,6 +166,8 @@ def paper_extract(stego: torch.Tensor, h: int, w: int, c: int, plane: int, lengt
         raise ValueError("stego must hold h*w*c bytes")
     if out is None:
         out = torch.empty(length, dtype=torch.uint8, device=stego.device)
+    if out.numel() < length:
+        raise ValueError("out must hold the %d data bytes" % length)
     check(lib().lsb_paper_extract(_u8(stego, "stego"), h, w, c, plane, _u8(out, "out") if length else None,
                                   length, _stream_ptr(stream)))
     return out
@@ -158,7 +194,7 @@ def extract_plane(stego: torch.Tensor, c: int, plane: int, k: int, out: torch.Te
         out = torch.empty(max(int(cap), 0), dtype=torch.uint8, device=stego.device)
     if len_status is None:
         len_status = torch.empty(2, dtype=torch.int32, device=stego.device)
-    base = len_status.data_ptr()
+    base = _len_status_ptr(len_status)
     check(lib().lsb_extract_plane(_u8(stego, "stego"), pixels, c, plane, k, _u8(out, "out") if out.numel() else None,
                                   out.numel(), ctypes.c_void_p(base), ctypes.c_void_p(base + 4),
                                   _stream_ptr(stream)))
@@ -171,7 +207,7 @@ def sse(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None, strea
         raise ValueError("a and b must have the same size")
     if out is None:
         out = torch.empty(1, dtype=torch.int64, device=a.device)
-    check(lib().lsb_sse(_u8(a, "a"), _u8(b, "b"), a.numel(), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    check(lib().lsb_sse(_u8(a, "a"), _u8(b, "b"), a.numel(), _word64_ptr(out, "out"), _stream_ptr(stream)))
     return out
 
 
@@ -193,6 +229,10 @@ def video_embed_host(host_frames: torch.Tensor, host_stego: torch.Tensor, frame_
             raise TypeError("%s must be a contiguous pinned uint8 host tensor" % name)
     if host_frames.numel() % frame_bytes or host_stego.numel() != host_frames.numel():
         raise ValueError("host buffers must hold whole frames, stego as many bytes as frames")
+    frames = host_frames.numel() // frame_bytes
+    if 1 <= k <= 8 and stream_bytes.numel() < _slice_stream_end(k, 0, frames * frame_bytes, stream_bits):
+        raise ValueError("stream_bytes holds %d bytes; the clip reads up to byte %d"
+                         % (stream_bytes.numel(), _slice_stream_end(k, 0, frames * frame_bytes, stream_bits)))
     streams = list(streams)
     slots = ring.numel() // frame_bytes // len(streams) * len(streams)
     if slots < 1:
@@ -212,7 +252,7 @@ def verify(cover: torch.Tensor, stego: torch.Tensor, msg: torch.Tensor, k: int,
     if out is None:
         out = torch.empty(1, dtype=torch.int64, device=cover.device)
     check(lib().lsb_verify(_u8(cover, "cover"), _u8(stego, "stego"), cover.numel(), _u8(msg, "msg"), msg.numel(), k,
-                           ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+                           _word64_ptr(out, "out"), _stream_ptr(stream)))
     return out
 
 

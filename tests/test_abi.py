@@ -115,3 +115,25 @@ def test_image_sizes_that_would_overflow_are_refused(lib):
     assert b"2^48" in lib.lsb_last_error()
     assert lib.lsb_embed_plane(None, None, 16, 65537, 0, None, 0, 1, None) == E_ARG
     assert lib.lsb_embed_plane(None, None, 2**48 + 1, 3, 0, None, 0, 1, None) == E_ARG
+
+
+def test_binding_checks_stream_buffer_sizes_before_calling(lib):
+    """A raw slice reads (embed) or writes (extract) stream bytes up to
+    ceil(min(k*(t0+n), stream_bits)/8); the binding refuses shorter stream
+    buffers before anything reaches the library (CPU tensors suffice: the
+    size check comes first)."""
+    import torch
+
+    from paper_0912_0947_amd import api
+
+    cover = torch.zeros(100, dtype=torch.uint8)
+    # k = 3, t0 = 100, n = 100: bits [300, 600) -> bytes up to 75
+    with pytest.raises(ValueError, match="75"):
+        api.embed_raw(cover, 100, torch.zeros(74, dtype=torch.uint8), 10**6, 3)
+    with pytest.raises(ValueError, match="75"):
+        api.extract_raw(cover, 100, torch.zeros(74, dtype=torch.uint8), 10**6, 3)
+    # the stream ends at bit 310: 39 bytes are enough, and the next check is the device one
+    with pytest.raises(TypeError, match="GPU"):
+        api.embed_raw(cover, 100, torch.zeros(39, dtype=torch.uint8), 310, 3)
+    with pytest.raises(ValueError):
+        api.paper_extract(torch.zeros(48, dtype=torch.uint8), 4, 4, 3, 0, 4, out=torch.zeros(3, dtype=torch.uint8))
