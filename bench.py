@@ -51,17 +51,22 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "plain_8192x8192x3_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0912_0947_amd", "csrc", f) for f in ("lsb_device.hpp", "lsb_plain.hip")]
 
 
-def _traffic_profile():
+BATCH_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "batched_4096_covers_traffic.md")
+BATCH_KERNEL_SOURCES = [os.path.join(ROOT, "paper_0912_0947_amd", "csrc", f)
+                        for f in ("lsb_device.hpp", "lsb_batch_device.hpp", "lsb_batch.hip", "lsb_batch_raw.hip")]
+
+
+def _traffic_profile(path=TRAFFIC_PROFILE, sources=KERNEL_SOURCES):
     """The committed counter profile's entries, or None when the kernel
     sources changed since it was taken."""
     import hashlib
     import re
 
-    if not os.path.exists(TRAFFIC_PROFILE):
+    if not os.path.exists(path):
         return None
-    text = open(TRAFFIC_PROFILE).read()
+    text = open(path).read()
     got = dict(re.findall(r"^(kernel|source_sha256|traffic_bytes_per_launch): (.+)$", text, flags=re.M))
-    sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
+    sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in sources)).hexdigest()
     if got.get("source_sha256") != sha:
         return None
     got["launches"] = {key: (name, int(b)) for key, name, b in
@@ -87,6 +92,27 @@ def stored_launch_traffic(launch: str, kernel: str):
         return None
     name, b = got["launches"].get(launch, (None, None))
     return b if name == kernel else None
+
+
+def stored_batch_traffic(launch: str):
+    """HBM bytes of one batched launch ("batched_embed", "batched_extract",
+    "clip_frames_embed", "clip_frames_extract") from the committed counter
+    profile, or None when the batched kernel sources changed since."""
+    got = _traffic_profile(BATCH_TRAFFIC_PROFILE, BATCH_KERNEL_SOURCES)
+    if got is None:
+        return None
+    return got["launches"].get(launch, (None, None))[1]
+
+
+def batched_roofline(bytes_, seconds, launch, clock):
+    """Achieved GB/s of one batched launch (algorithmic bytes over `seconds`,
+    measured by `clock`: "stream events" around the graph launch, or "wall"
+    including the host's enqueue), its fraction of the 8 TB/s HBM peak, and
+    its counter traffic if the profile is current."""
+    achieved = bytes_ / seconds / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_batch_traffic(launch),
+            "algorithmic_bytes": int(bytes_), "clock": clock}
 
 
 def launch_kernel_name(api, op: str, k: int, n: int) -> str:
@@ -240,6 +266,8 @@ def bench_batched(api, batch, dev, log_fn, reps=3):
         wall, gpu = timed(fn)
         res[name] = {"wall_ms": round(wall * 1e3, 3), "gpu_ms": round(gpu * 1e3, 3),
                      "GBps_wall": round(b / wall / 1e9, 1)}
+        if name.startswith("batched"):
+            res[name]["roofline"] = batched_roofline(b, gpu, name, "stream events")
         log_fn("%s: %.2f ms wall (%.1f GB/s)" % (name, wall * 1e3, b / wall / 1e9))
     assert bool((status == 0).all()) and bool((ls[:, 1] == 0).all())
     assert torch.equal(out, msg), "batched/loop extract lost messages"
@@ -594,7 +622,8 @@ def bench_video(api, lib_handle, dev, log_fn, frames=600, h=1080, w=1920):
     finally:
         plan.close()
     res["device_per_frame_batched"] = {"launches": 1, "jobs": frames, "ms": round(t * 1e3, 3),
-                                       "GBps": round((2 * n + ln + 4) / t / 1e9, 1)}
+                                       "GBps": round((2 * n + ln + 4) / t / 1e9, 1),
+                                       "roofline": batched_roofline(2 * n + ln + 4, t, "clip_frames_embed", "wall")}
     # extraction of the same stream: whole clip in one launch (header decoded
     # on the device), 600 raw per-frame launches, 600 raw extract jobs of one
     # plan; algorithmic bytes F + len (the F = 8 |S| carrying bytes, then the message)
@@ -622,7 +651,8 @@ def bench_video(api, lib_handle, dev, log_fn, frames=600, h=1080, w=1920):
     finally:
         plan.close()
     res["device_per_frame_batched_extract"] = {"launches": 1, "jobs": frames, "ms": round(t * 1e3, 3),
-                                               "GBps": round(xb / t / 1e9, 1)}
+                                               "GBps": round(xb / t / 1e9, 1),
+                                               "roofline": batched_roofline(xb, t, "clip_frames_extract", "wall")}
     del out, back
     host = torch.empty(n, dtype=torch.uint8, pin_memory=True)
     host.copy_(clip)

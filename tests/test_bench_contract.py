@@ -76,3 +76,19 @@ def test_single_thread_oracle_leg_repeats_to_its_time_floor():
     many = bench.cpu_baseline(cover, msgs, min_seconds=1e9, max_steps=3)
     assert many["sample"].startswith("3 full steps:")
     assert one["value"] > 0 and many["value"] > 0
+
+
+def test_batched_traffic_entries_are_current():
+    """While the committed counter profile of the batched kernels matches
+    their sources, the bench reads a traffic figure per batched launch, the
+    clip's within 1 % of its algorithmic bytes."""
+    alg = {"clip_frames_embed": 7698240000, "clip_frames_extract": 2099519996}
+    if bench.stored_batch_traffic("batched_embed") is None:
+        pytest.skip("batched kernel sources changed since the counters were taken: retake them")
+    for launch in ("batched_embed", "batched_extract", "clip_frames_embed", "clip_frames_extract"):
+        t = bench.stored_batch_traffic(launch)
+        assert isinstance(t, int) and t > 0, launch
+        if launch in alg:
+            assert abs(t / alg[launch] - 1) < 0.01, launch
+    r = bench.batched_roofline(8e9, 2e-3, "batched_embed", "stream events")
+    assert r["achieved"] == 4000.0 and r["frac"] == 0.5 and r["bound"] == "hbm"
