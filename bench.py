@@ -933,7 +933,7 @@ def main():
         del pool
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on one step ...")
+        log("timing the CPU oracle on whole steps (at least 10 s), one thread ...")
         result["cpu_baseline"] = cpu_baseline(cover_np, msgs_np)
         result["cpu_baseline"]["cpu_model"] = cpu_model()
         threads = max(1, min(16, os.cpu_count() or 1))
