@@ -44,8 +44,10 @@ def test_timed_launch_records_the_kernel():
     torch.cuda.synchronize()
     ms = a.elapsed_time(b)
     assert ms != before, "the events were not recorded by the launch"
-    # 2n bytes moved: above 8 TB/s is impossible, a whole millisecond is far off
-    assert 2 * n / 8e12 * 1e3 < ms < 1.0, ms
+    # the kernel's own span: more than a microsecond for 2n bytes (the cover
+    # may still sit in the 256 MB last-level cache, so no HBM bound is
+    # assumed), and far below the 1 GiB fill the events first spanned
+    assert 0.001 < ms < min(1.0, before), (ms, before)
 
 
 @pytest.mark.parametrize("case", ["bad k", "empty raw slice", "capacity", "no stream bits to extract"])
