@@ -118,6 +118,15 @@ int lsb_extract_raw(const uint8_t *stego, uint64_t n, uint64_t t0,
                     uint8_t *stream_out, uint64_t stream_bits, int k,
                     void *stream);
 
+/* Bytes of a logical stream that a raw slice touches, counted from stream
+ * byte 0: ceil(min(k*(t0+n), stream_bits) / 8), or 0 when the slice carries
+ * no stream bit (k*(t0+n) <= k*t0 or stream_bits <= k*t0).  The stream
+ * buffer passed to lsb_embed_raw / lsb_extract_raw must hold at least this
+ * many bytes.  LSB_E_ARG for k outside 1..8 or t0, n, stream_bits beyond
+ * the raw calls' ranges (2^56, 2^56, 2^60).  Host-only. */
+int64_t lsb_slice_stream_bytes(int k, uint64_t t0, uint64_t n,
+                               uint64_t stream_bits);
+
 /* ------------------------------------------------------------------------
  * The paper's own layout (Section VI steps 2-7, Section VII steps 2-6), kept
  * for fidelity: 2 bits per byte in ONE colour plane `plane` of an h x w x c
@@ -280,6 +289,19 @@ int lsb_embed_batch(lsb_plan *plan, const uint8_t *cover_arena,
 int lsb_extract_batch(lsb_plan *plan, const uint8_t *stego_arena,
                       uint8_t *msg_arena, uint32_t *len_dev,
                       int32_t *status_dev, void *stream);
+
+/* Arena extents of a job list: extents[0], [1], [2] receive one past the
+ * furthest byte that any job reads or writes in the cover, stego and message
+ * arenas (0 when none).  A job of n = 0 touches nothing; a header embed job
+ * over its capacity reads no message byte (it gets LSB_E_CAPACITY and no
+ * work) but still counts in the cover and stego extents; a header extract
+ * job writes at most
+ * min(msg_cap, capacity) bytes; a raw job reads or writes stream bytes up to
+ * lsb_slice_stream_bytes.  `op` as for lsb_plan_create.  LSB_E_ARG for a
+ * bad k or op, or offsets of 2^62 and beyond.  Host-only: callers check arena sizes
+ * with it before lsb_plan_run, which trusts them. */
+int lsb_job_extents(const lsb_job *jobs, int n_jobs, int op,
+                    uint64_t *extents);
 
 /* Total tiles (work units) of the current job list, for reporting. */
 int64_t lsb_plan_tiles(const lsb_plan *plan);

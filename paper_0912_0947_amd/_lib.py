@@ -102,6 +102,8 @@ SIGNATURES = {
     "lsb_embed_batch": (_I, [_P, _P, _P, _P, _P, _P]),
     "lsb_extract_batch": (_I, [_P, _P, _P, _P, _P, _P]),
     "lsb_plan_tiles": (_I64, [_P]),
+    "lsb_job_extents": (_I, [ctypes.POINTER(Job), _I, _I, ctypes.POINTER(_U64)]),
+    "lsb_slice_stream_bytes": (_I64, [_I, _U64, _U64, _U64]),
     "lsb_plan_destroy": (None, [_P]),
     "lsb_tune_get": (_I, [_I, _I, _U64, ctypes.POINTER(LaunchCfg)]),
     "lsb_tune_set": (_I, [_I, _I, _I, ctypes.POINTER(LaunchCfg)]),

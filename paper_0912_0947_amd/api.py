@@ -62,10 +62,9 @@ def _word64_ptr(t: torch.Tensor, name: str) -> ctypes.c_void_p:
 
 
 def _slice_stream_end(k: int, t0: int, n: int, stream_bits: int) -> int:
-    """One past the last stream byte that cover bytes [t0, t0 + n) touch:
-    ceil(min(k*(t0 + n), stream_bits) / 8), or 0 when they carry no bit."""
-    end = min(k * (t0 + n), stream_bits)
-    return -(-end // 8) if end > k * t0 else 0
+    """One past the last stream byte that cover bytes [t0, t0 + n) touch, or
+    0 when they carry no bit (lsb_slice_stream_bytes)."""
+    return check(lib().lsb_slice_stream_bytes(k, t0, n, stream_bits))
 
 
 def capacity(n: int, k: int) -> int:

@@ -27,32 +27,16 @@ def make_jobs(count: int) -> np.ndarray:
 
 def _extents(jobs: np.ndarray, op_mode: int) -> tuple[int, int, int]:
     """Bytes that the cover, stego and message arenas must hold for ``jobs``:
-    one past the furthest byte that any job reads or writes in each."""
+    one past the furthest byte that any job reads or writes in each, as the
+    library computes it (lsb_job_extents)."""
     if not jobs.size:
         return 0, 0, 0
+    jobs = np.ascontiguousarray(jobs, dtype=JOB_DTYPE)
     if max(int(jobs[f].max()) for f in ("cover_off", "stego_off", "msg_off")) >= 1 << 62:
         raise ValueError("a job offset lies beyond any device arena")
-    op = jobs["op"] if op_mode == OP_MIXED else np.full(jobs.size, op_mode, np.uint8)
-    raw = (jobs["flags"] & JOB_RAW) != 0
-    n, k = jobs["n"], jobs["k"].astype(np.uint64)
-    # raw slices: stream bytes [k*t0/8, ceil(min(k*(t0+n), stream_bits)/8)) of the stream at msg_off
-    begin = k * jobs["t0"]
-    end = np.minimum(k * (jobs["t0"] + n), jobs["stream_bits"])
-    raw_bytes = np.where(end > begin, (end + 7) // 8, 0)
-    # header jobs: at most the message capacity of the cover
-    room = n * k // 8
-    cap = np.minimum(np.where(room >= 4, room - 4, 0), 0xFFFFFFFF)
-    ln = jobs["len"].astype(np.uint64)
-    header_bytes = np.where(op == OP_EMBED, np.where(ln <= cap, ln, 0), np.minimum(jobs["msg_cap"], cap))
-    msg_bytes = np.where(raw, raw_bytes, header_bytes)
-    busy = n > 0
-    emb = busy & (op == OP_EMBED)
-
-    def reach(off, size, mask):
-        return int((off + size)[mask].max()) if mask.any() else 0
-
-    return (reach(jobs["cover_off"], n, emb), reach(jobs["stego_off"], n, busy),
-            reach(jobs["msg_off"], msg_bytes, msg_bytes > 0))
+    ext = (ctypes.c_uint64 * 3)()
+    check(lib().lsb_job_extents(jobs.ctypes.data_as(ctypes.POINTER(Job)), int(jobs.size), int(op_mode), ext))
+    return int(ext[0]), int(ext[1]), int(ext[2])
 
 
 def _ptr(t, name: str, need: int = 0, dtypes=(torch.uint8,)):

@@ -27,6 +27,11 @@ HIPCC_FLAGS = [
 ]
 
 
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+# roctx ranges around the serving loop's phases (rocprofv3 --marker-trace)
+LINK_FLAGS = ["-L" + ROCM_LIB, "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + ROCM_LIB]
+
+
 def sources() -> list[str]:
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
@@ -66,7 +71,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         msg = "\n".join("%s:\n%s" % (s, o) for s, o in failed)
         raise RuntimeError("hipcc failed:\n" + msg)
     tmp = LIB + ".tmp%d" % os.getpid()
-    subprocess.check_call([hipcc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp, *objs])
+    subprocess.check_call([hipcc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp, *objs, *LINK_FLAGS])
     os.replace(tmp, LIB)
     if verbose:
         print("built %s in %.1f s" % (LIB, time.time() - t0), flush=True)

@@ -84,6 +84,7 @@ struct lsb_plan {
     uint8_t *host = nullptr;  // pinned mirror of the device table
     uint8_t *dev = nullptr;
     hipEvent_t done = nullptr;  // recorded after each run
+    hipStream_t last_stream = nullptr;  // stream of the last run
     bool ran = false;
     // graph state
     hipGraph_t graph = nullptr;
@@ -341,6 +342,46 @@ int lsb_plan_update(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
 
 int64_t lsb_plan_tiles(const lsb_plan *p) { return p ? (int64_t)p->total_tiles : fail(LSB_E_ARG, "null plan"); }
 
+int lsb_job_extents(const lsb_job *jobs, int n_jobs, int op, uint64_t *extents) {
+    clear_error();
+    if (!extents || (n_jobs && !jobs) || n_jobs < 0) return fail(LSB_E_ARG, "lsb_job_extents: null argument");
+    if (op != LSB_OP_EMBED && op != LSB_OP_EXTRACT && op != LSB_OP_MIXED)
+        return fail(LSB_E_ARG, "lsb_job_extents: op=%d", op);
+    uint64_t cover = 0, stego = 0, msg = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        const lsb_job &J = jobs[i];
+        if (J.k < 1 || J.k > 8) return fail(LSB_E_ARG, "job %d: k=%d outside 1..8", i, (int)J.k);
+        const uint8_t jop = op == LSB_OP_MIXED ? J.op : (uint8_t)op;
+        if (jop != LSB_OP_EMBED && jop != LSB_OP_EXTRACT) return fail(LSB_E_ARG, "job %d: bad op %d", i, (int)J.op);
+        if (J.n > (1ull << 48) || J.cover_off >= (1ull << 62) || J.stego_off >= (1ull << 62) ||
+            J.msg_off >= (1ull << 62) || J.t0 > (1ull << 56) || J.stream_bits > (1ull << 60))
+            return fail(LSB_E_ARG, "job %d: offset or size out of range", i);
+        if (!J.n) continue;
+        const uint64_t k = J.k;
+        uint64_t mbytes;  // message-arena bytes from msg_off that the job reads or writes
+        if (J.flags & LSB_JOB_RAW) {
+            // stream bytes k*t0/8 .. ceil(min(k*(t0+n), stream_bits)/8) - 1
+            const uint64_t begin = k * J.t0;
+            uint64_t end = k * (J.t0 + J.n);
+            if (end > J.stream_bits) end = J.stream_bits;
+            mbytes = end > begin ? ceil_div(end, 8) : 0;
+        } else {
+            const uint64_t room = room_bytes(J.n, J.k);
+            uint64_t cap = room >= 4 ? room - 4 : 0;
+            if (cap > 0xFFFFFFFFull) cap = 0xFFFFFFFFull;
+            if (jop == LSB_OP_EMBED) mbytes = (uint64_t)J.len <= cap ? J.len : 0;  // over capacity: no work
+            else mbytes = J.msg_cap < cap ? J.msg_cap : cap;
+        }
+        if (jop == LSB_OP_EMBED && J.cover_off + J.n > cover) cover = J.cover_off + J.n;
+        if (J.stego_off + J.n > stego) stego = J.stego_off + J.n;
+        if (mbytes && J.msg_off + mbytes > msg) msg = J.msg_off + mbytes;
+    }
+    extents[0] = cover;
+    extents[1] = stego;
+    extents[2] = msg;
+    return LSB_OK;
+}
+
 int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, uint8_t *msg_arena, uint32_t *len_dev,
                  int32_t *status_dev, void *stream) {
     clear_error();
@@ -349,6 +390,7 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
     if (!status_dev) return fail(LSB_E_ARG, "lsb_plan_run: null status_dev");
     if (p->has_extract && !len_dev) return fail(LSB_E_ARG, "lsb_plan_run: extract jobs need len_dev");
     if (!stego_arena || !msg_arena) return fail(LSB_E_ARG, "lsb_plan_run: null arena");
+    if (p->has_embed && !cover_arena) return fail(LSB_E_ARG, "lsb_plan_run: embed jobs need a cover arena");
     if (((uintptr_t)cover_arena | (uintptr_t)stego_arena | (uintptr_t)msg_arena) & 255)
         return fail(LSB_E_ARG, "lsb_plan_run: arena base pointers must be 256-byte aligned");
     int dev = -1;
@@ -390,7 +432,14 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
     p->args.status = status_dev;
     int rc = prepare_graph(p);
     if (rc != LSB_OK) return rc;
-    hipError_t e = hipGraphLaunch(p->exec, (hipStream_t)stream);
+    hipError_t e;
+    if (p->ran && (hipStream_t)stream != p->last_stream) {
+        // every run shares the device job table and its tile counter: a run
+        // on another stream starts only after the previous run has finished
+        e = hipStreamWaitEvent((hipStream_t)stream, p->done, 0);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent(plan)");
+    }
+    e = hipGraphLaunch(p->exec, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     e = hipEventRecord(p->done, (hipStream_t)stream);
     if (e != hipSuccess) {
@@ -400,6 +449,7 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
         return hip_fail(e, "hipEventRecord(plan)");
     }
     p->ran = true;
+    p->last_stream = (hipStream_t)stream;
     return LSB_OK;
 }
 

@@ -276,6 +276,16 @@ int64_t lsb_capacity(uint64_t n, int k) {
     return (int64_t)cap;
 }
 
+int64_t lsb_slice_stream_bytes(int k, uint64_t t0, uint64_t n, uint64_t stream_bits) {
+    if (k < 1 || k > 8) return fail(LSB_E_ARG, "lsb_slice_stream_bytes: k=%d outside 1..8", k);
+    if (t0 > (1ull << 56) || n > (1ull << 56) || stream_bits > (1ull << 60))
+        return fail(LSB_E_ARG, "lsb_slice_stream_bytes: t0/n/stream_bits out of range");
+    const uint64_t begin = (uint64_t)k * t0;
+    uint64_t end = (uint64_t)k * (t0 + n);
+    if (end > stream_bits) end = stream_bits;
+    return end > begin ? (int64_t)ceil_div(end, 8) : 0;
+}
+
 int lsb_embed(const uint8_t *cover, uint8_t *stego, uint64_t n, const uint8_t *msg, uint32_t len, int k,
               void *stream) {
     const TimedCall timed_call;

@@ -28,11 +28,25 @@
 #include <map>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "lsb_host.hpp"
 
 using namespace lsb;
 
 namespace {
+
+// roctx range over one phase of a loop iteration (admission, launch,
+// completion), so that a trace taken with rocprofv3 --marker-trace shows
+// where the host thread spends its time.  Without a profiler attached a
+// range costs two calls into the roctx library.
+class PhaseRange {
+   public:
+    explicit PhaseRange(const char *name) { roctxRangePushA(name); }
+    ~PhaseRange() { roctxRangePop(); }
+    PhaseRange(const PhaseRange &) = delete;
+    PhaseRange &operator=(const PhaseRange &) = delete;
+};
 
 constexpr uint64_t kNone = ~0ull;
 constexpr uint64_t kAlign = 256;
@@ -110,6 +124,9 @@ class HipExecutor : public Executor {
     HipExecutor(const lsb_server_cfg *cfg, int slots, int batch) : cfg_(cfg), B_(batch), s_(slots) {
         t0_ = std::chrono::steady_clock::now();
     }
+    // The run's clock starts here, once the slots are set up, so that the
+    // first arrivals are not charged for stream, event and plan creation.
+    void start_clock() { t0_ = std::chrono::steady_clock::now(); }
     ~HipExecutor() override {
         for (S &s : s_) {
             // teardown: nothing useful can be done with a failure here.  A
@@ -255,9 +272,11 @@ class SimExecutor : public Executor {
 
 int check_args(const lsb_server_cfg *cfg, const lsb_request *req, int n_req, lsb_result *res, bool device) {
     if (!cfg || (!req && n_req) || (!res && n_req) || n_req < 0) return fail(LSB_E_ARG, "lsb_serve: null argument");
-    if (device && (!cfg->arena || ((uintptr_t)cfg->arena & 255) || ((uintptr_t)cfg->cover_pool & 255) ||
-                   ((uintptr_t)cfg->msg_pool & 255)))
-        return fail(LSB_E_ARG, "lsb_serve: arena and pools must be 256-byte aligned device buffers");
+    // any request may be served as an embed (an extract with nothing resident
+    // is), so both pools are always needed
+    if (device && (!cfg->arena || !cfg->cover_pool || !cfg->msg_pool || ((uintptr_t)cfg->arena & 255) ||
+                   ((uintptr_t)cfg->cover_pool & 255) || ((uintptr_t)cfg->msg_pool & 255)))
+        return fail(LSB_E_ARG, "lsb_serve: arena and pools must be non-null, 256-byte aligned device buffers");
     if (cfg->max_batch < 1 || cfg->max_batch > 65536 || cfg->n_slots < 1 || cfg->n_slots > 16 || cfg->reserved)
         return fail(LSB_E_ARG, "lsb_serve: max_batch 1..65536, n_slots 1..16, reserved 0");
     for (int i = 0; i < n_req; ++i) {
@@ -301,6 +320,7 @@ int run_scheduler(const lsb_server_cfg *cfg, const lsb_request *req, int n_req, 
     int next = 0, finished = 0, rc = LSB_OK;
     int64_t launches = 0, evictions = 0, stalls = 0, rejected = 0, batched = 0;
     bool stalled = false;
+    bool released = false;  // a completion released memory since the last admission pass
     double bytes = 0, first_arrival = n_req ? req[0].arrival_s : 0, last_done = 0;
     auto in_flight = [&]() {
         for (int s = 0; s < S; ++s)
@@ -319,32 +339,67 @@ int run_scheduler(const lsb_server_cfg *cfg, const lsb_request *req, int n_req, 
         bool progressed = false;
         while (next < n_req && req[next].arrival_s <= now) waiting.push_back(next++);
 
-        // ---- admission, in arrival order, against the HBM budget
-        while (!waiting.empty()) {
-            const int i = waiting.front();
-            const lsb_request &q = req[i];
-            lsb_result &r = res[i];
-            int target = -1;
-            size_t target_pos = 0;  // where the claimed stego sat in `live`
-            if (q.op == LSB_OP_EXTRACT) {
-                if (q.target >= 0) {
-                    if (sv[q.target].live) {
-                        target = (int)q.target;
-                        const auto it = std::find(live.begin(), live.end(), target);
-                        target_pos = (size_t)(it - live.begin());
-                        live.erase(it);
+        // ---- admission, in arrival order, against the HBM budget.  After a
+        // stall the head of the queue can only fit once a completion has
+        // released memory, so admission waits for one.
+        if (!waiting.empty() && !(stalled && !released)) {
+            released = false;
+            const PhaseRange admit_range("lsb_serve:admit");
+            while (!waiting.empty()) {
+                const int i = waiting.front();
+                const lsb_request &q = req[i];
+                lsb_result &r = res[i];
+                int target = -1;
+                size_t target_pos = 0;  // where the claimed stego sat in `live`
+                if (q.op == LSB_OP_EXTRACT) {
+                    if (q.target >= 0) {
+                        if (sv[q.target].live) {
+                            target = (int)q.target;
+                            const auto it = std::find(live.begin(), live.end(), target);
+                            target_pos = (size_t)(it - live.begin());
+                            live.erase(it);
+                        }
+                    } else if (!live.empty()) {
+                        target = live.front();
+                        live.pop_front();
                     }
-                } else if (!live.empty()) {
-                    target = live.front();
-                    live.pop_front();
+                    if (target >= 0) sv[target].live = false;  // claimed by this extract
                 }
-                if (target >= 0) sv[target].live = false;  // claimed by this extract
-            }
-            if (target < 0) {  // served as an embed: its message must fit its cover
-                const uint64_t room = room_bytes(q.n, q.k);
-                if (room < 4 || q.len > room - 4) {  // fails alone, at admission
-                    r.status = LSB_E_CAPACITY;
-                    r.op_run = LSB_OP_EMBED;
+                if (target < 0) {  // served as an embed: its message must fit its cover
+                    const uint64_t room = room_bytes(q.n, q.k);
+                    if (room < 4 || q.len > room - 4) {  // fails alone, at admission
+                        r.status = LSB_E_CAPACITY;
+                        r.op_run = LSB_OP_EMBED;
+                        r.done_s = now;
+                        ++rejected;
+                        ++finished;
+                        waiting.pop_front();
+                        progressed = true;
+                        continue;
+                    }
+                }
+                const uint64_t need = target >= 0 ? res[target].len : q.n;
+                uint64_t off = 0;
+                bool ok = arena.alloc(need, &off);
+                while (!ok && !cfg->keep_outputs && !live.empty()) {  // evict the oldest resident stego
+                    const int v = live.front();
+                    live.pop_front();
+                    sv[v].live = false;
+                    release_out(v);
+                    ++evictions;
+                    ok = arena.alloc(need, &off);
+                }
+                if (!ok) {
+                    if (target >= 0) {  // give the claim back, at its place in the age order
+                        sv[target].live = true;
+                        live.insert(live.begin() + (std::ptrdiff_t)std::min(target_pos, live.size()), target);
+                    }
+                    if (in_flight()) {
+                        if (!stalled) ++stalls;
+                        stalled = true;
+                        break;  // wait for completions to free memory
+                    }
+                    r.status = LSB_E_NOMEM;  // can never fit the budget
                     r.done_s = now;
                     ++rejected;
                     ++finished;
@@ -352,56 +407,28 @@ int run_scheduler(const lsb_server_cfg *cfg, const lsb_request *req, int n_req, 
                     progressed = true;
                     continue;
                 }
-            }
-            const uint64_t need = target >= 0 ? res[target].len : q.n;
-            uint64_t off = 0;
-            bool ok = arena.alloc(need, &off);
-            while (!ok && !cfg->keep_outputs && !live.empty()) {  // evict the oldest resident stego
-                const int v = live.front();
-                live.pop_front();
-                sv[v].live = false;
-                release_out(v);
-                ++evictions;
-                ok = arena.alloc(need, &off);
-            }
-            if (!ok) {
-                if (target >= 0) {  // give the claim back, at its place in the age order
-                    sv[target].live = true;
-                    live.insert(live.begin() + (std::ptrdiff_t)std::min(target_pos, live.size()), target);
-                }
-                if (in_flight()) {
-                    if (!stalled) ++stalls;
-                    stalled = true;
-                    break;  // wait for completions to free memory
-                }
-                r.status = LSB_E_NOMEM;  // can never fit the budget
-                r.done_s = now;
-                ++rejected;
-                ++finished;
+                stalled = false;
                 waiting.pop_front();
                 progressed = true;
-                continue;
+                r.admit_s = now;
+                r.out_off = off;
+                sv[i].out_bytes = need;
+                if (target >= 0) {
+                    r.op_run = LSB_OP_EXTRACT;
+                    r.target = target;
+                    r.k = res[target].k;
+                } else {
+                    r.op_run = LSB_OP_EMBED;
+                    r.len = q.len;
+                }
+                ready.push_back(i);
             }
-            stalled = false;
-            waiting.pop_front();
-            progressed = true;
-            r.admit_s = now;
-            r.out_off = off;
-            sv[i].out_bytes = need;
-            if (target >= 0) {
-                r.op_run = LSB_OP_EXTRACT;
-                r.target = target;
-                r.k = res[target].k;
-            } else {
-                r.op_run = LSB_OP_EMBED;
-                r.len = q.len;
-            }
-            ready.push_back(i);
         }
 
         // ---- launch admitted requests on free slots
         for (int s = 0; s < S && !ready.empty() && rc == LSB_OK; ++s) {
             if (busy[s]) continue;
+            const PhaseRange launch_range("lsb_serve:launch");
             slot_reqs[0][s].clear();
             slot_reqs[1][s].clear();
             for (int c = 0; c < B && !ready.empty(); ++c) {
@@ -450,7 +477,9 @@ int run_scheduler(const lsb_server_cfg *cfg, const lsb_request *req, int n_req, 
             bool done = false;
             rc = ex.poll(s, &done);
             if (rc != LSB_OK || !done) continue;
+            const PhaseRange complete_range("lsb_serve:complete");
             busy[s] = false;
+            released = true;
             progressed = true;
             now = ex.now();
             for (int op = 0; op < 2; ++op) {
@@ -539,6 +568,7 @@ extern "C" int lsb_serve(const lsb_server_cfg *cfg, const lsb_request *req, int 
     HipExecutor ex(cfg, cfg->n_slots, cfg->max_batch);
     rc = ex.init(st, ln);
     if (rc != LSB_OK) return rc;
+    ex.start_clock();
     return run_scheduler(cfg, req, n_req, res, stats, ex, arena);
 }
 

@@ -40,7 +40,8 @@ static const any_fn entry_points[] = {
     (any_fn)lsb_tune_get,       (any_fn)lsb_tune_set,        (any_fn)lsb_autotune,
     (any_fn)lsb_batch_tune_get, (any_fn)lsb_batch_tune_set,  (any_fn)lsb_serve,
     (any_fn)lsb_time_next_launch, (any_fn)lsb_stream_reference, (any_fn)lsb_serve_simulate,
-    (any_fn)lsb_last_error,     (any_fn)lsb_version,
+    (any_fn)lsb_last_error,     (any_fn)lsb_version,         (any_fn)lsb_job_extents,
+    (any_fn)lsb_slice_stream_bytes,
 };
 
 static int check(int cond, const char *what) {
@@ -61,6 +62,50 @@ int main(void) {
     bad += check(lsb_capacity(100, 9) == LSB_E_ARG && lsb_last_error()[0] != '\0', "k outside 1..8");
     bad += check(lsb_paper_capacity(7, 1024) == 7 * 256, "paper-layout capacity");
     bad += check(lsb_version() != NULL && strlen(lsb_version()) > 0, "version string");
+
+    /* stream bytes a raw slice touches: ceil(min(k*(t0+n), bits) / 8) */
+    bad += check(lsb_slice_stream_bytes(1, 0, 100, 4000) == 13, "slice stream bytes, k = 1");
+    bad += check(lsb_slice_stream_bytes(2, 4, 10, 1000) == 4, "slice stream bytes, k = 2, t0 = 4");
+    bad += check(lsb_slice_stream_bytes(3, 10, 50, 30) == 0, "slice past the stream touches nothing");
+    bad += check(lsb_slice_stream_bytes(9, 0, 1, 8) == LSB_E_ARG, "slice stream bytes, bad k");
+
+    /* arena extents of a job list */
+    {
+        lsb_job jobs[2];
+        uint64_t ext[3] = {0, 0, 0};
+        memset(jobs, 0, sizeof jobs);
+        jobs[0].cover_off = 0;      jobs[0].stego_off = 512;  jobs[0].msg_off = 0;
+        jobs[0].n = 1000;           jobs[0].len = 100;        jobs[0].k = 1; /* capacity 121 */
+        jobs[1].cover_off = 4096;   jobs[1].stego_off = 0;    jobs[1].msg_off = 256;
+        jobs[1].n = 100;            jobs[1].len = 30;         jobs[1].k = 1; /* capacity 8: no work */
+        bad += check(lsb_job_extents(jobs, 2, LSB_OP_EMBED, ext) == LSB_OK, "job extents");
+        bad += check(ext[0] == 4196 && ext[1] == 1512 && ext[2] == 100, "embed extents");
+        jobs[0].msg_cap = 500;      jobs[1].msg_cap = 3;
+        bad += check(lsb_job_extents(jobs, 2, LSB_OP_EXTRACT, ext) == LSB_OK, "extract extents");
+        bad += check(ext[0] == 0 && ext[1] == 1512 && ext[2] == 259, "extract extents: min(msg_cap, capacity)");
+        jobs[1].k = 0;
+        bad += check(lsb_job_extents(jobs, 2, LSB_OP_EMBED, ext) == LSB_E_ARG, "extents refuse k = 0");
+    }
+
+    /* the serving loop refuses a null cover pool before touching a device */
+    {
+        lsb_server_cfg cfg;
+        lsb_request req;
+        lsb_result res;
+        memset(&cfg, 0, sizeof cfg);
+        memset(&req, 0, sizeof req);
+        cfg.arena = (uint8_t *)(uintptr_t)4096; /* never dereferenced: the call fails first */
+        cfg.arena_bytes = 1u << 20;
+        cfg.msg_pool = (const uint8_t *)(uintptr_t)8192;
+        cfg.max_batch = 1;
+        cfg.n_slots = 1;
+        req.n = 4096;
+        req.k = 1;
+        bad += check(lsb_serve(&cfg, &req, 1, &res, NULL) == LSB_E_ARG, "serve refuses a null cover pool");
+        cfg.cover_pool = (const uint8_t *)(uintptr_t)8192;
+        cfg.msg_pool = NULL;
+        bad += check(lsb_serve(&cfg, &req, 1, &res, NULL) == LSB_E_ARG, "serve refuses a null message pool");
+    }
 
     /* tuning tables round trip */
     {
