@@ -197,14 +197,31 @@ int lsb_video_embed_host(const uint8_t *host_frames, uint8_t *host_stego,
                          void *const *streams, int n_streams);
 
 /* ------------------------------------------------------------------------
- * Verification in one launch: *mismatches_dev (overwritten) receives the
- * number of bytes t < n where stego[t] differs from what lsb_embed(cover,
- * msg, len, k) writes (Section VI step 7 recomputed from cover and message).
- * Zero means stego carries exactly msg, so extraction (Section VII step 6)
- * returns it.  Reads cover, stego and the stream once; writes one counter. */
+ * Round-trip checks in one launch (extraction, Section VII step 6, is the
+ * reverse of embedding, Section VI step 7).  A stego byte is counted as
+ * wrong unless (a) the bits of its field that carry stream bits, read back
+ * as extraction reads them, equal those bits of S = BE32(len) || msg, and
+ * (b) every other bit equals the cover byte's (bytes past the stream: the
+ * whole byte).  Both checks run on the extraction side of the method, so a
+ * wrong embedding is caught, not reproduced.  *mismatches_dev (a device
+ * word, overwritten) receives the count; 0 means that extraction returns msg
+ * and that the stego differs from the cover only where the stream is.
+ * Errors as lsb_embed (k, capacity, null or overlapping buffers, also the
+ * counter overlapping any buffer).
+ *
+ * lsb_verify: checks an existing stego buffer (read only).  Reads cover,
+ * stego and the stream once (2n + |S| bytes).
+ *
+ * lsb_embed_verify: lsb_embed(cover, stego, n, msg, len, k) and, in the same
+ * launch, the check of every byte it writes (each vector is extracted again
+ * in registers right after it is embedded).  stego == cover is the in-place
+ * form.  Same memory traffic as lsb_embed (2n + |S|; in place 2F + |S|). */
 int lsb_verify(const uint8_t *cover, const uint8_t *stego, uint64_t n,
                const uint8_t *msg, uint32_t len, int k,
                uint64_t *mismatches_dev, void *stream);
+int lsb_embed_verify(const uint8_t *cover, uint8_t *stego, uint64_t n,
+                     const uint8_t *msg, uint32_t len, int k,
+                     uint64_t *mismatches_dev, void *stream);
 
 /* ------------------------------------------------------------------------
  * Batched form: thousands of covers of uneven size and k in one persistent

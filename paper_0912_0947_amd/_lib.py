@@ -96,6 +96,7 @@ SIGNATURES = {
     "lsb_sse": (_I, [_P, _P, _U64, _P, _P]),
     "lsb_video_embed_host": (_I, [_P, _P, _U64, _U64, _P, _U64, _I, _P, _U32, ctypes.POINTER(_P), _I]),
     "lsb_verify": (_I, [_P, _P, _U64, _P, _U32, _I, _P, _P]),
+    "lsb_embed_verify": (_I, [_P, _P, _U64, _P, _U32, _I, _P, _P]),
     "lsb_plan_create": (_I, [ctypes.POINTER(_P), ctypes.POINTER(Job), _I, _I]),
     "lsb_plan_update": (_I, [_P, ctypes.POINTER(Job), _I]),
     "lsb_plan_run": (_I, [_P, _P, _P, _P, _P, _P, _P]),

@@ -14,7 +14,7 @@ from ._lib import (E_ARG, OK, OP_EMBED, OP_EXTRACT, LaunchCfg, LsbError, check, 
 
 __all__ = ["capacity", "embed", "extract", "extract_sync", "embed_raw", "extract_raw",
            "paper_capacity", "paper_embed", "paper_extract", "embed_plane", "extract_plane", "sse", "psnr",
-           "video_embed_host", "verify", "stream_reference",
+           "video_embed_host", "verify", "embed_verify", "stream_reference",
            "tune_get", "tune_set", "autotune", "LsbError", "OK", "OP_EMBED", "OP_EXTRACT"]
 
 
@@ -245,7 +245,8 @@ def video_embed_host(host_frames: torch.Tensor, host_stego: torch.Tensor, frame_
 def verify(cover: torch.Tensor, stego: torch.Tensor, msg: torch.Tensor, k: int,
            out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Count (on the device, int64 tensor of 1 element) the stego bytes that
-    differ from the embedding of ``msg`` into ``cover``; 0 means verified."""
+    fail the round-trip check against ``cover`` and ``msg`` (lsb_verify);
+    0 means verified."""
     if cover.numel() != stego.numel():
         raise ValueError("cover and stego must have the same size")
     if out is None:
@@ -253,6 +254,22 @@ def verify(cover: torch.Tensor, stego: torch.Tensor, msg: torch.Tensor, k: int,
     check(lib().lsb_verify(_u8(cover, "cover"), _u8(stego, "stego"), cover.numel(), _u8(msg, "msg"), msg.numel(), k,
                            _word64_ptr(out, "out"), _stream_ptr(stream)))
     return out
+
+
+def embed_verify(cover: torch.Tensor, msg: torch.Tensor, k: int, out: torch.Tensor | None = None,
+                 mismatches: torch.Tensor | None = None, stream=None):
+    """Embed as ``embed`` and, in the same launch, check every written byte
+    through extraction.  Returns (stego, mismatches): ``mismatches`` is an
+    int64 device tensor of 1 element holding the number of wrong bytes (0
+    for a correct embedding).  ``out`` may be ``cover`` itself (in place)."""
+    stego = torch.empty_like(cover) if out is None else out
+    if stego.numel() != cover.numel():
+        raise ValueError("out must have as many bytes as cover")
+    if mismatches is None:
+        mismatches = torch.empty(1, dtype=torch.int64, device=cover.device)
+    check(lib().lsb_embed_verify(_u8(cover, "cover"), _u8(stego, "out"), cover.numel(), _u8(msg, "msg"),
+                                 msg.numel(), k, _word64_ptr(mismatches, "mismatches"), _stream_ptr(stream)))
+    return stego, mismatches
 
 
 def stream_reference(kind: int, src: torch.Tensor, dst: torch.Tensor, side: torch.Tensor | None = None,

@@ -41,7 +41,7 @@ static const any_fn entry_points[] = {
     (any_fn)lsb_batch_tune_get, (any_fn)lsb_batch_tune_set,  (any_fn)lsb_serve,
     (any_fn)lsb_time_next_launch, (any_fn)lsb_stream_reference, (any_fn)lsb_serve_simulate,
     (any_fn)lsb_last_error,     (any_fn)lsb_version,         (any_fn)lsb_job_extents,
-    (any_fn)lsb_slice_stream_bytes,
+    (any_fn)lsb_slice_stream_bytes, (any_fn)lsb_embed_verify,
 };
 
 static int check(int cond, const char *what) {

@@ -43,3 +43,86 @@ def test_verify_after_device_embed_and_in_place():
     assert torch.equal(buf, stego)
     stego[123456789] ^= 1
     assert int(api.verify(cover, stego, msg, k).item()) == 1
+
+
+@pytest.mark.parametrize("k", range(1, 9))
+@pytest.mark.parametrize("n,off,inplace", [(33, 0, False), (1000, 3, False), (65543, 0, True),
+                                           ((1 << 20) + 13, 0, False), ((1 << 20) + 13, 0, True),
+                                           (3000001, 7, False)])
+def test_embed_verify_round_trip(k, n, off, inplace):
+    """The fused embed + extraction check: the stego equals the oracle's
+    embedding byte for byte and the round trip finds no wrong byte, at every
+    k, ragged sizes, misaligned pointers and in place."""
+    cover = inputs.random_bytes(n, 2021, k, n)
+    cap = oracle.capacity(n, k)
+    if cap < 0:
+        pytest.skip("no room for a header")
+    msg = inputs.random_bytes(int(inputs.rng(2022, k, n).integers(0, cap + 1)), 2023, k, n)
+    rc, want = oracle.embed(cover, msg, k)
+    assert rc == oracle.OK
+    c_d = to_dev(cover, pad_before=off, pad_after=16)
+    if inplace:
+        stego, bad = api.embed_verify(c_d, to_dev(msg), k, out=c_d)
+    else:
+        stego, bad = api.embed_verify(c_d, to_dev(msg), k, out=to_dev(np.zeros(n, np.uint8), pad_before=off))
+    torch.cuda.synchronize()
+    assert int(bad.item()) == 0
+    assert np.array_equal(stego.cpu().numpy(), want)
+
+
+def _corrupt_cases(stego, cover, k, msg_len, seed):
+    """Host-side corruptions of a correct stego, each aimed at one kind of
+    bit: the stream field, the bits above it, bytes past the stream, the
+    header's fields and (for a partial last field) the cover bits it keeps."""
+    g = inputs.rng(seed, k, stego.size)
+    n = stego.size
+    F = -(-8 * (4 + msg_len) // k)  # cover bytes that carry the stream
+    low = (1 << k) - 1
+    cases = {}
+    idx = g.choice(F, size=min(F, 41), replace=False)
+    b = stego.copy()
+    b[idx] ^= np.uint8(1 << int(g.integers(0, k)))  # one field bit each
+    cases["field"] = b
+    if k < 8:
+        b = stego.copy()
+        b[idx] ^= np.uint8(0x80)  # the top bit, above every field
+        cases["above"] = b
+    if F < n:
+        past = g.choice(np.arange(F, n), size=min(n - F, 29), replace=False)
+        b = stego.copy()
+        b[past] ^= np.uint8(low)  # past the stream: the low bits must be the cover's
+        cases["past"] = b
+    b = stego.copy()
+    b[: -(-32 // k)] ^= np.uint8(1 << (k - 1))  # every header field
+    cases["header"] = b
+    nb = (8 * (4 + msg_len)) % k
+    if nb:  # partial last field: its low k - nb bits are the cover's
+        b = stego.copy()
+        b[F - 1] ^= np.uint8(1)
+        cases["partial"] = b
+    return cases
+
+
+@pytest.mark.parametrize("k", range(1, 9))
+def test_verify_counts_each_kind_of_corruption(k):
+    """lsb_verify on host-corrupted stego bytes: each corruption kind is
+    counted byte for byte against the oracle's stego, and the uncorrupted
+    stego counts zero."""
+    n = 100003
+    cover = inputs.random_bytes(n, 2031, k)
+    cap = oracle.capacity(n, k)
+    ln = cap // 2
+    if k in (3, 5, 6, 7):  # a length whose stream ends inside a field
+        ln = cap - 1
+        while (8 * (4 + ln)) % k == 0:
+            ln -= 1
+    msg = inputs.random_bytes(ln, 2032, k)
+    rc, stego = oracle.embed(cover, msg, k)
+    assert rc == oracle.OK
+    c_d, m_d = to_dev(cover), to_dev(msg)
+    assert int(api.verify(c_d, to_dev(stego), m_d, k).item()) == 0
+    for name, bad in _corrupt_cases(stego, cover, k, ln, 2033).items():
+        want = int(np.count_nonzero(bad != stego))
+        assert want > 0
+        got = int(api.verify(c_d, to_dev(bad), m_d, k).item())
+        assert got == want, "k=%d %s: counted %d of %d wrong bytes" % (k, name, got, want)
