@@ -320,6 +320,26 @@ int lsb_extract_batch(lsb_plan *plan, const uint8_t *stego_arena,
 int lsb_job_extents(const lsb_job *jobs, int n_jobs, int op,
                     uint64_t *extents);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops that may not call hipMalloc): lsb_plan_create + lsb_plan_run in one
+ * call that allocates nothing.  The job table and its tile counter go into a
+ * fixed device array of the library (one per device, about 256 KiB, held
+ * until the process ends) instead of plan memory; the table is staged in a
+ * library host buffer and uploaded with an asynchronous copy on `stream`,
+ * then the prologue and persistent kernels are launched on `stream` (no
+ * graph).  Jobs, arenas, len_dev and status_dev mean what they mean for
+ * lsb_plan_create(op) + lsb_plan_run, and the results are identical.
+ * At most LSB_STATIC_MAX_JOBS jobs: more is LSB_E_ARG (use a plan).  Every
+ * call on one device shares that device's table: calls on one stream run in
+ * order, but calls on different streams of one device whose work overlaps
+ * race and must not be made.  Host threads are serialised while the table is
+ * filled and uploaded. */
+enum { LSB_STATIC_MAX_JOBS = 4096 };
+int lsb_batch_run_static(const lsb_job *jobs, int n_jobs, int op,
+                         const uint8_t *cover_arena, uint8_t *stego_arena,
+                         uint8_t *msg_arena, uint32_t *len_dev,
+                         int32_t *status_dev, void *stream);
+
 /* Total tiles (work units) of the current job list, for reporting. */
 int64_t lsb_plan_tiles(const lsb_plan *plan);
 

@@ -25,6 +25,7 @@ OP_EMBED = 0
 OP_EXTRACT = 1
 OP_MIXED = 2
 JOB_RAW = 1  # lsb_job.flags: raw slice, no header
+STATIC_MAX_JOBS = 4096  # LSB_STATIC_MAX_JOBS
 REF_COPY, REF_EMBED_MIX, REF_EXTRACT_MIX = 0, 1, 2
 
 ERROR_NAMES = {
@@ -103,6 +104,7 @@ SIGNATURES = {
     "lsb_embed_batch": (_I, [_P, _P, _P, _P, _P, _P]),
     "lsb_extract_batch": (_I, [_P, _P, _P, _P, _P, _P]),
     "lsb_plan_tiles": (_I64, [_P]),
+    "lsb_batch_run_static": (_I, [ctypes.POINTER(Job), _I, _I, _P, _P, _P, _P, _P, _P]),
     "lsb_job_extents": (_I, [ctypes.POINTER(Job), _I, _I, ctypes.POINTER(_U64)]),
     "lsb_slice_stream_bytes": (_I64, [_I, _U64, _U64, _U64]),
     "lsb_plan_destroy": (None, [_P]),

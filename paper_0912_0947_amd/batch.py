@@ -7,7 +7,7 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import JOB_RAW, OP_EMBED, OP_EXTRACT, OP_MIXED, Job, LaunchCfg, check, lib
+from ._lib import JOB_RAW, OP_EMBED, OP_EXTRACT, OP_MIXED, STATIC_MAX_JOBS, Job, LaunchCfg, check, lib
 
 ALIGN = 256
 
@@ -148,6 +148,24 @@ class Plan:
             pass
 
 
+def run_static(jobs: np.ndarray, op: int, cover_arena, stego_arena, msg_arena, len_dev, status_dev,
+               stream=None) -> None:
+    """lsb_batch_run_static: run ``jobs`` (at most STATIC_MAX_JOBS) as a plan
+    created with ``op`` would, without allocating anything: the job table
+    goes to the library's fixed device array.  Same checks of the arenas and
+    result arrays as Plan.run."""
+    jobs = np.ascontiguousarray(jobs, dtype=JOB_DTYPE)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    c, st, m = _extents(jobs, int(op))
+    n = int(jobs.size)
+    check(lib().lsb_batch_run_static(jobs.ctypes.data_as(ctypes.POINTER(Job)) if n else None, n, int(op),
+                                     _ptr(cover_arena, "cover_arena", c), _ptr(stego_arena, "stego_arena", st),
+                                     _ptr(msg_arena, "msg_arena", m),
+                                     _ptr(len_dev, "len_dev", n if len_dev is not None else 0, _WORD),
+                                     _ptr(status_dev, "status_dev", n, _WORD), ctypes.c_void_p(stream.cuda_stream)))
+
+
 def tune_get():
     cfg = LaunchCfg()
     tv = ctypes.c_int64()
@@ -160,5 +178,5 @@ def tune_set(block: int, unroll: int, blocks_per_cu: int, nontemporal: int, tile
     check(lib().lsb_batch_tune_set(ctypes.byref(cfg), int(tile_vectors)))
 
 
-__all__ = ["Plan", "make_jobs", "align_up", "JOB_DTYPE", "JOB_RAW", "OP_EMBED", "OP_EXTRACT", "OP_MIXED", "tune_get",
-           "tune_set"]
+__all__ = ["Plan", "make_jobs", "align_up", "run_static", "JOB_DTYPE", "JOB_RAW", "OP_EMBED", "OP_EXTRACT", "OP_MIXED",
+           "STATIC_MAX_JOBS", "tune_get", "tune_set"]

@@ -173,6 +173,182 @@ static int prepare_graph(lsb_plan *p) {
     return LSB_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Table of lsb_batch_run_static: the job table and tile counter live in this
+// file-scope device array (one copy per device, held until the process
+// ends) instead of plan memory.  Host code never uses the array's name as an
+// address: static_table() looks up each device's copy once, with that
+// device current, and the launches take that pointer.
+constexpr size_t kStaticTableBytes = sizeof(PlanHeader) + sizeof(DevJob) * ((size_t)LSB_STATIC_MAX_JOBS + 1);
+static __device__ __align__(256) uint8_t scratch[kStaticTableBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_static_mu;                    // guards the two below and the launches' upload order
+static uint8_t *g_static_dev[kMaxDevices] = {};  // device address of `scratch`, per device
+alignas(256) static uint8_t g_static_host[kStaticTableBytes];  // host staging of the table
+
+// Device address of the current device's copy of `scratch` (caller holds
+// g_static_mu).
+static int static_table(uint8_t **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(LSB_E_ARG, "lsb_batch_run_static: device %d not supported", dev);
+    if (!g_static_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+        g_static_dev[dev] = (uint8_t *)ptr;
+    }
+    *out = g_static_dev[dev];
+    return LSB_OK;
+}
+
+// Host-side checks of a job list (nothing is touched on failure).
+static int validate_jobs(const lsb_job *jobs, int n_jobs, int op_mode) {
+    for (int i = 0; i < n_jobs; ++i) {
+        const lsb_job &J = jobs[i];
+        if (J.k < 1 || J.k > 8) return fail(LSB_E_ARG, "job %d: k=%d outside 1..8", i, (int)J.k);
+        if (op_mode == LSB_OP_MIXED && J.op != LSB_OP_EMBED && J.op != LSB_OP_EXTRACT)
+            return fail(LSB_E_ARG, "job %d: bad op %d", i, (int)J.op);
+        if ((J.cover_off | J.stego_off | J.msg_off) & 255)
+            return fail(LSB_E_ARG, "job %d: arena offsets must be multiples of 256", i);
+        if (J.n > (1ull << 48)) return fail(LSB_E_ARG, "job %d: n out of range", i);
+        if (J.reserved) return fail(LSB_E_ARG, "job %d: reserved field must be 0", i);
+        if (J.flags & ~LSB_JOB_RAW) return fail(LSB_E_ARG, "job %d: unknown flags 0x%x", i, (unsigned)J.flags);
+        if (!(J.flags & LSB_JOB_RAW)) {
+            if (J.t0 || J.stream_bits) return fail(LSB_E_ARG, "job %d: t0/stream_bits set on a header job", i);
+            continue;
+        }
+        if (J.t0 > (1ull << 56) || J.stream_bits > (1ull << 60))
+            return fail(LSB_E_ARG, "job %d: t0/stream_bits out of range", i);
+        const uint8_t op = op_mode == LSB_OP_MIXED ? J.op : (uint8_t)op_mode;
+        if (op == LSB_OP_EXTRACT) {
+            // slices of one stream may not share an output byte
+            const uint64_t begin = (uint64_t)J.k * J.t0;
+            uint64_t end = (uint64_t)J.k * (J.t0 + J.n);
+            if (end > J.stream_bits) end = J.stream_bits;
+            if (begin % 8) return fail(LSB_E_ARG, "job %d: raw extract with k*t0 not byte aligned", i);
+            if (begin < end && end % 8 && end != J.stream_bits)
+                return fail(LSB_E_ARG, "job %d: raw extract ends inside a stream byte", i);
+        }
+    }
+    return LSB_OK;
+}
+
+// What a filled job table holds, for the launch.
+struct TableInfo {
+    uint64_t tiles = 0;
+    bool has_extract = false, has_embed = false, has_raw = false;
+    int cls = 0;            // kernel class (see lsb_batch_device.hpp)
+    size_t used_bytes = 0;  // header + (n_jobs + 1) records
+};
+
+// Fill a job table (header, records, sentinel) at `host` for validated
+// jobs: per-job status for work the host can already refuse, tile counts
+// and their exclusive prefix, the kernel class.  The header's tile counter
+// is zero, so uploading the table resets it.
+static TableInfo fill_table(const lsb_job *jobs, int n_jobs, int op_mode, int64_t tv, uint8_t *host) {
+    PlanHeader *h = (PlanHeader *)host;
+    DevJob *d = (DevJob *)(host + sizeof(PlanHeader));
+    TableInfo t;
+    uint64_t tiles = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        const lsb_job &J = jobs[i];
+        const uint8_t op = op_mode == LSB_OP_MIXED ? J.op : (uint8_t)op_mode;
+        DevJob &D = d[i];
+        memset(&D, 0, sizeof D);
+        D.cover_off = J.cover_off;
+        D.stego_off = J.stego_off;
+        D.msg_off = J.msg_off;
+        D.n = J.n;
+        D.raw = (J.flags & LSB_JOB_RAW) ? 1 : 0;
+        t.has_raw |= D.raw != 0;
+        D.len = D.raw ? 0 : J.len;  // what the prologue reports in len_dev
+        D.k = J.k;
+        D.op = op;
+        D.tile_begin = tiles;
+        D.status = LSB_OK;
+        uint64_t vectors = ceil_div(J.n, 16);
+        if (D.raw) {
+            D.t0 = J.t0;
+            if (op == LSB_OP_EMBED) {
+                t.has_embed = true;
+                D.cap_bits = J.stream_bits;  // stream bits past the slice fall back to copies
+            } else {
+                t.has_extract = true;
+                const uint64_t begin = (uint64_t)J.k * J.t0;
+                uint64_t end = (uint64_t)J.k * (J.t0 + J.n);
+                if (end > J.stream_bits) end = J.stream_bits;
+                D.cap_bits = end;
+                // only the fields that carry stream bits [begin, end) are read
+                const uint64_t fields = end > begin ? ceil_div(end - begin, (uint64_t)J.k) : 0;
+                const uint64_t v_stream = ceil_div(fields, 16);
+                if (v_stream < vectors) vectors = v_stream;
+            }
+        } else if (op == LSB_OP_EMBED) {
+            D.cap_bits = 0;
+            t.has_embed = true;
+            const uint64_t room = room_bytes(J.n, J.k);
+            if (room < 4 || (uint64_t)J.len > room - 4) {
+                D.status = LSB_E_CAPACITY;
+                vectors = 0;
+            }
+        } else {
+            t.has_extract = true;
+            D.cap_bits = J.msg_cap;
+            // worst case: the stream may fill the cover or the output buffer
+            const uint64_t room = room_bytes(J.n, J.k);
+            const uint64_t cap = room >= 4 ? room - 4 : 0;
+            const uint64_t max_len = J.msg_cap < cap ? J.msg_cap : cap;
+            const uint64_t v_stream = ceil_div(4 + max_len, 2 * (uint64_t)J.k);
+            if (v_stream < vectors) vectors = v_stream;
+            if ((uint64_t)J.k * J.n < 32) vectors = 0;
+        }
+        // an extract tile moves about half the bytes of an embed tile (no
+        // stego write), so it covers twice the vectors to carry the same
+        // traffic per job lookup
+        const uint64_t jtv = op == LSB_OP_EMBED ? (uint64_t)tv : 2 * (uint64_t)tv;
+        tiles += ceil_div(vectors, jtv);
+    }
+    DevJob &S = d[n_jobs];  // sentinel
+    memset(&S, 0, sizeof S);
+    S.tile_begin = tiles;
+    memset(h, 0, sizeof *h);
+    h->n_jobs = (uint64_t)n_jobs;
+    h->total_tiles = tiles;
+    h->tile_vectors = (uint64_t)tv;
+    t.tiles = tiles;
+    if (n_jobs > 0) {
+        bool same = true;
+        bool same_op = true;
+        for (int i = 1; i < n_jobs && same; ++i) same = d[i].op == d[0].op && d[i].k == d[0].k;
+        for (int i = 1; i < n_jobs && same_op; ++i) same_op = d[i].op == d[0].op;
+        if (same) t.cls = 1 + 8 * d[0].op + (d[0].k - 1);
+        else if (same_op && d[0].op == LSB_OP_EXTRACT) t.cls = kClsExtractAnyK;
+    }
+    t.used_bytes = sizeof(PlanHeader) + sizeof(DevJob) * ((size_t)n_jobs + 1);
+    return t;
+}
+
+// Grids of the persistent kernel (capped at blocks_per_cu blocks per CU,
+// never more blocks than tiles) and of the prologue (one wave per job, 4
+// waves per block).
+static unsigned main_grid_for(const lsb_launch_cfg &cfg, uint64_t total_tiles) {
+    const uint64_t cap_blocks = (uint64_t)(cfg.blocks_per_cu > 0 ? cfg.blocks_per_cu : 8) * (uint64_t)device_cus();
+    return (unsigned)(total_tiles < cap_blocks ? (total_tiles ? total_tiles : 1) : cap_blocks);
+}
+
+static unsigned prologue_grid_for(int n_jobs) {
+    const uint64_t g = ceil_div((uint64_t)n_jobs, 4);
+    return (unsigned)(g > 4096 ? 4096 : (g ? g : 1));
+}
+
+static int64_t batch_tile_vectors() {
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    return g_tile_vectors;
+}
+
 extern "C" {
 
 int lsb_plan_create(lsb_plan **out, const lsb_job *jobs, int n_jobs, int op) {
@@ -215,128 +391,24 @@ int lsb_plan_update(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
     if (n_jobs < 0 || n_jobs > p->max_jobs)
         return fail(LSB_E_ARG, "lsb_plan_update: n_jobs=%d outside 0..%d", n_jobs, p->max_jobs);
     if (n_jobs && !jobs) return fail(LSB_E_ARG, "lsb_plan_update: null job list");
-    int64_t tv;
-    {
-        std::lock_guard<std::mutex> g(g_batch_mu);
-        tv = g_tile_vectors;
-    }
+    const int64_t tv = batch_tile_vectors();
     // validate everything before touching the mirror
-    for (int i = 0; i < n_jobs; ++i) {
-        const lsb_job &J = jobs[i];
-        if (J.k < 1 || J.k > 8) return fail(LSB_E_ARG, "job %d: k=%d outside 1..8", i, (int)J.k);
-        if (p->op_mode == LSB_OP_MIXED && J.op != LSB_OP_EMBED && J.op != LSB_OP_EXTRACT)
-            return fail(LSB_E_ARG, "job %d: bad op %d", i, (int)J.op);
-        if ((J.cover_off | J.stego_off | J.msg_off) & 255)
-            return fail(LSB_E_ARG, "job %d: arena offsets must be multiples of 256", i);
-        if (J.n > (1ull << 48)) return fail(LSB_E_ARG, "job %d: n out of range", i);
-        if (J.reserved) return fail(LSB_E_ARG, "job %d: reserved field must be 0", i);
-        if (J.flags & ~LSB_JOB_RAW) return fail(LSB_E_ARG, "job %d: unknown flags 0x%x", i, (unsigned)J.flags);
-        if (!(J.flags & LSB_JOB_RAW)) {
-            if (J.t0 || J.stream_bits) return fail(LSB_E_ARG, "job %d: t0/stream_bits set on a header job", i);
-            continue;
-        }
-        if (J.t0 > (1ull << 56) || J.stream_bits > (1ull << 60))
-            return fail(LSB_E_ARG, "job %d: t0/stream_bits out of range", i);
-        const uint8_t op = p->op_mode == LSB_OP_MIXED ? J.op : (uint8_t)p->op_mode;
-        if (op == LSB_OP_EXTRACT) {
-            // slices of one stream may not share an output byte
-            const uint64_t begin = (uint64_t)J.k * J.t0;
-            uint64_t end = (uint64_t)J.k * (J.t0 + J.n);
-            if (end > J.stream_bits) end = J.stream_bits;
-            if (begin % 8) return fail(LSB_E_ARG, "job %d: raw extract with k*t0 not byte aligned", i);
-            if (begin < end && end % 8 && end != J.stream_bits)
-                return fail(LSB_E_ARG, "job %d: raw extract ends inside a stream byte", i);
-        }
-    }
+    const int rc = validate_jobs(jobs, n_jobs, p->op_mode);
+    if (rc != LSB_OK) return rc;
     // the previous run's upload must have read the mirror before it changes
     if (p->ran) {
         hipError_t e = hipEventSynchronize(p->done);
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(plan)");
     }
-    PlanHeader *h = (PlanHeader *)p->host;
-    DevJob *d = (DevJob *)(p->host + sizeof(PlanHeader));
-    uint64_t tiles = 0;
-    bool has_extract = false, has_embed = false, has_raw = false;
-    for (int i = 0; i < n_jobs; ++i) {
-        const lsb_job &J = jobs[i];
-        const uint8_t op = p->op_mode == LSB_OP_MIXED ? J.op : (uint8_t)p->op_mode;
-        DevJob &D = d[i];
-        memset(&D, 0, sizeof D);
-        D.cover_off = J.cover_off;
-        D.stego_off = J.stego_off;
-        D.msg_off = J.msg_off;
-        D.n = J.n;
-        D.raw = (J.flags & LSB_JOB_RAW) ? 1 : 0;
-        has_raw |= D.raw != 0;
-        D.len = D.raw ? 0 : J.len;  // what the prologue reports in len_dev
-        D.k = J.k;
-        D.op = op;
-        D.tile_begin = tiles;
-        D.status = LSB_OK;
-        uint64_t vectors = ceil_div(J.n, 16);
-        if (D.raw) {
-            D.t0 = J.t0;
-            if (op == LSB_OP_EMBED) {
-                has_embed = true;
-                D.cap_bits = J.stream_bits;  // stream bits past the slice fall back to copies
-            } else {
-                has_extract = true;
-                const uint64_t begin = (uint64_t)J.k * J.t0;
-                uint64_t end = (uint64_t)J.k * (J.t0 + J.n);
-                if (end > J.stream_bits) end = J.stream_bits;
-                D.cap_bits = end;
-                // only the fields that carry stream bits [begin, end) are read
-                const uint64_t fields = end > begin ? ceil_div(end - begin, (uint64_t)J.k) : 0;
-                const uint64_t v_stream = ceil_div(fields, 16);
-                if (v_stream < vectors) vectors = v_stream;
-            }
-        } else if (op == LSB_OP_EMBED) {
-            D.cap_bits = 0;
-            has_embed = true;
-            const uint64_t room = room_bytes(J.n, J.k);
-            if (room < 4 || (uint64_t)J.len > room - 4) {
-                D.status = LSB_E_CAPACITY;
-                vectors = 0;
-            }
-        } else {
-            has_extract = true;
-            D.cap_bits = J.msg_cap;
-            // worst case: the stream may fill the cover or the output buffer
-            const uint64_t room = room_bytes(J.n, J.k);
-            const uint64_t cap = room >= 4 ? room - 4 : 0;
-            const uint64_t max_len = J.msg_cap < cap ? J.msg_cap : cap;
-            const uint64_t v_stream = ceil_div(4 + max_len, 2 * (uint64_t)J.k);
-            if (v_stream < vectors) vectors = v_stream;
-            if ((uint64_t)J.k * J.n < 32) vectors = 0;
-        }
-        // an extract tile moves about half the bytes of an embed tile (no
-        // stego write), so it covers twice the vectors to carry the same
-        // traffic per job lookup
-        const uint64_t jtv = op == LSB_OP_EMBED ? (uint64_t)tv : 2 * (uint64_t)tv;
-        tiles += ceil_div(vectors, jtv);
-    }
-    DevJob &S = d[n_jobs];  // sentinel
-    memset(&S, 0, sizeof S);
-    S.tile_begin = tiles;
-    h->n_jobs = (uint64_t)n_jobs;
-    h->total_tiles = tiles;
-    h->tile_vectors = (uint64_t)tv;
+    const TableInfo t = fill_table(jobs, n_jobs, p->op_mode, tv, p->host);
     p->n_jobs = n_jobs;
-    p->total_tiles = tiles;
-    p->has_extract = has_extract;
-    p->has_embed = has_embed;
-    p->has_raw = has_raw;
-    p->cls = 0;
-    if (n_jobs > 0) {
-        bool same = true;
-        bool same_op = true;
-        for (int i = 1; i < n_jobs && same; ++i) same = d[i].op == d[0].op && d[i].k == d[0].k;
-        for (int i = 1; i < n_jobs && same_op; ++i) same_op = d[i].op == d[0].op;
-        if (same) p->cls = 1 + 8 * d[0].op + (d[0].k - 1);
-        else if (same_op && d[0].op == LSB_OP_EXTRACT) p->cls = kClsExtractAnyK;
-    }
+    p->total_tiles = t.tiles;
+    p->has_extract = t.has_extract;
+    p->has_embed = t.has_embed;
+    p->has_raw = t.has_raw;
+    p->cls = t.cls;
     p->tile_vectors = tv;
-    p->used_bytes = sizeof(PlanHeader) + sizeof(DevJob) * ((size_t)n_jobs + 1);
+    p->used_bytes = t.used_bytes;
     return LSB_OK;
 }
 
@@ -419,10 +491,8 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
     }
     p->cfg = cfg;
     p->fn = fn;
-    const uint64_t cap_blocks = (uint64_t)(cfg.blocks_per_cu > 0 ? cfg.blocks_per_cu : 8) * (uint64_t)device_cus();
-    p->main_grid = (unsigned)(p->total_tiles < cap_blocks ? (p->total_tiles ? p->total_tiles : 1) : cap_blocks);
-    p->pro_grid = (unsigned)ceil_div((uint64_t)p->n_jobs, 4);  // 4 waves per block, one job per wave
-    if (p->pro_grid > 4096) p->pro_grid = 4096;
+    p->main_grid = main_grid_for(cfg, p->total_tiles);
+    p->pro_grid = prologue_grid_for(p->n_jobs);
     p->args.hdr = (const PlanHeader *)p->dev;
     p->args.jobs = (const DevJob *)(p->dev + sizeof(PlanHeader));
     p->args.cover = cover_arena;
@@ -482,6 +552,56 @@ void lsb_plan_destroy(lsb_plan *p) {
     if (p->dev) (void)hipFree(p->dev);
     if (p->host) (void)hipHostFree(p->host);
     delete p;
+}
+
+int lsb_batch_run_static(const lsb_job *jobs, int n_jobs, int op, const uint8_t *cover_arena,
+                         uint8_t *stego_arena, uint8_t *msg_arena, uint32_t *len_dev, int32_t *status_dev,
+                         void *stream) {
+    clear_error();
+    if (op != LSB_OP_EMBED && op != LSB_OP_EXTRACT && op != LSB_OP_MIXED)
+        return fail(LSB_E_ARG, "lsb_batch_run_static: op=%d", op);
+    if (n_jobs < 0 || n_jobs > LSB_STATIC_MAX_JOBS)
+        return fail(LSB_E_ARG, "lsb_batch_run_static: n_jobs=%d outside 0..%d (larger batches need a plan)", n_jobs,
+                    LSB_STATIC_MAX_JOBS);
+    if (n_jobs == 0) return LSB_OK;
+    if (!jobs) return fail(LSB_E_ARG, "lsb_batch_run_static: null job list");
+    if (!status_dev) return fail(LSB_E_ARG, "lsb_batch_run_static: null status_dev");
+    if (!stego_arena || !msg_arena) return fail(LSB_E_ARG, "lsb_batch_run_static: null arena");
+    if (((uintptr_t)cover_arena | (uintptr_t)stego_arena | (uintptr_t)msg_arena) & 255)
+        return fail(LSB_E_ARG, "lsb_batch_run_static: arena base pointers must be 256-byte aligned");
+    int rc = validate_jobs(jobs, n_jobs, op);
+    if (rc != LSB_OK) return rc;
+    lsb_launch_cfg cfg;
+    int64_t tv;
+    {
+        std::lock_guard<std::mutex> g(g_batch_mu);
+        cfg = g_batch_cfg;
+        tv = g_tile_vectors;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    // One host staging table for all devices: filled and uploaded under the
+    // lock.  An upload from pageable memory has read the source when
+    // hipMemcpyAsync returns, so the next call may refill it.
+    std::lock_guard<std::mutex> g(g_static_mu);
+    uint8_t *table = nullptr;
+    rc = static_table(&table);
+    if (rc != LSB_OK) return rc;
+    const TableInfo t = fill_table(jobs, n_jobs, op, tv, g_static_host);
+    if (t.has_extract && !len_dev) return fail(LSB_E_ARG, "lsb_batch_run_static: extract jobs need len_dev");
+    if (t.has_embed && !cover_arena) return fail(LSB_E_ARG, "lsb_batch_run_static: embed jobs need a cover arena");
+    hipError_t e = hipMemcpyAsync(table, g_static_host, t.used_bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(static job table)");
+    const PlanHeader *hdr = (const PlanHeader *)table;
+    const DevJob *dj = (const DevJob *)(table + sizeof(PlanHeader));
+    void *pro_args[] = {&hdr, &dj, &stego_arena, &len_dev, &status_dev};
+    e = hipLaunchKernel((const void *)lsb_batch_prologue, dim3(prologue_grid_for(n_jobs)), dim3(256), pro_args, 0,
+                        st);
+    if (e != hipSuccess) return hip_fail(e, "prologue launch");
+    const BatchFn fn = batch_fn(cfg.unroll, cfg.nontemporal, t.cls, t.has_raw);
+    void *main_args[] = {&hdr, &dj, &cover_arena, &stego_arena, &msg_arena, &len_dev, &status_dev};
+    e = hipLaunchKernel((const void *)fn, dim3(main_grid_for(cfg, t.tiles)), dim3(cfg.block), main_args, 0, st);
+    if (e != hipSuccess) return hip_fail(e, "persistent kernel launch");
+    return LSB_OK;
 }
 
 int lsb_batch_tune_get(lsb_launch_cfg *cfg, int64_t *tile_vectors) {

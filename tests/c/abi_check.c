@@ -41,7 +41,7 @@ static const any_fn entry_points[] = {
     (any_fn)lsb_batch_tune_get, (any_fn)lsb_batch_tune_set,  (any_fn)lsb_serve,
     (any_fn)lsb_time_next_launch, (any_fn)lsb_stream_reference, (any_fn)lsb_serve_simulate,
     (any_fn)lsb_last_error,     (any_fn)lsb_version,         (any_fn)lsb_job_extents,
-    (any_fn)lsb_slice_stream_bytes, (any_fn)lsb_embed_verify,
+    (any_fn)lsb_slice_stream_bytes, (any_fn)lsb_embed_verify,  (any_fn)lsb_batch_run_static,
 };
 
 static int check(int cond, const char *what) {
@@ -68,6 +68,11 @@ int main(void) {
     bad += check(lsb_slice_stream_bytes(2, 4, 10, 1000) == 4, "slice stream bytes, k = 2, t0 = 4");
     bad += check(lsb_slice_stream_bytes(3, 10, 50, 30) == 0, "slice past the stream touches nothing");
     bad += check(lsb_slice_stream_bytes(9, 0, 1, 8) == LSB_E_ARG, "slice stream bytes, bad k");
+
+    /* the allocation-free batched call refuses more jobs than its table
+     * before touching a device */
+    bad += check(lsb_batch_run_static(NULL, LSB_STATIC_MAX_JOBS + 1, LSB_OP_EMBED, NULL, NULL, NULL, NULL, NULL,
+                                      NULL) == LSB_E_ARG, "static batch refuses n_jobs > LSB_STATIC_MAX_JOBS");
 
     /* arena extents of a job list */
     {
