@@ -374,10 +374,21 @@ int lsb_autotune(int op, int k, uint64_t n, uint8_t *cover, uint8_t *stego,
 
 /* Batched-kernel configuration: tile size in 16-byte vectors per embed tile
  * (extract tiles span twice as many; a multiple of 64 in [64, 2^30]), the
- * kernel's block/unroll/nontemporal choice and its grid cap.  Plans read the
- * tile size at lsb_plan_update and the rest at each run. */
+ * kernel's block/unroll/nontemporal choice and its grid cap.  Blocks need at
+ * least 128 threads: one wave of each block hands out the tiles that the
+ * others stream.  Plans read the tile size at lsb_plan_update and the rest
+ * at each run. */
 int lsb_batch_tune_get(lsb_launch_cfg *cfg, int64_t *tile_vectors);
 int lsb_batch_tune_set(const lsb_launch_cfg *cfg, int64_t tile_vectors);
+
+/* The batched kernel keeps two launch shapes: one for plans with embed jobs
+ * (op = LSB_OP_EMBED, also used by mixed plans) and one for extract-only
+ * plans (op = LSB_OP_EXTRACT), which move about half the bytes per vector
+ * and do best with more vectors in flight per lane.  lsb_batch_tune_get
+ * returns the embed shape and lsb_batch_tune_set sets both (and the tile
+ * size); these read or set one. */
+int lsb_batch_tune_get_op(int op, lsb_launch_cfg *cfg);
+int lsb_batch_tune_set_op(int op, const lsb_launch_cfg *cfg);
 
 /* ------------------------------------------------------------------------
  * Serving loop: an open-loop stream of embed and extract requests served

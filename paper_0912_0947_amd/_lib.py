@@ -114,6 +114,8 @@ SIGNATURES = {
                           ctypes.POINTER(ctypes.c_double), _P]),
     "lsb_batch_tune_get": (_I, [ctypes.POINTER(LaunchCfg), ctypes.POINTER(_I64)]),
     "lsb_batch_tune_set": (_I, [ctypes.POINTER(LaunchCfg), _I64]),
+    "lsb_batch_tune_get_op": (_I, [_I, ctypes.POINTER(LaunchCfg)]),
+    "lsb_batch_tune_set_op": (_I, [_I, ctypes.POINTER(LaunchCfg)]),
     "lsb_serve": (_I, [ctypes.POINTER(ServerCfg), _P, _I, _P, ctypes.POINTER(ServeStats)]),
     "lsb_serve_simulate": (_I, [ctypes.POINTER(ServerCfg), _P, _I, _P, ctypes.POINTER(ServeStats),
                                 ctypes.c_double, ctypes.c_double]),

@@ -174,9 +174,40 @@ def tune_get():
 
 
 def tune_set(block: int, unroll: int, blocks_per_cu: int, nontemporal: int, tile_vectors: int) -> None:
+    """Set the launch shape of every plan (embed and extract) and the tile size."""
     cfg = LaunchCfg(block, unroll, blocks_per_cu, nontemporal, 0)
     check(lib().lsb_batch_tune_set(ctypes.byref(cfg), int(tile_vectors)))
 
 
+def tune_get_op(op: int) -> dict:
+    """Launch shape of plans with embed jobs (OP_EMBED) or of extract-only plans (OP_EXTRACT)."""
+    cfg = LaunchCfg()
+    check(lib().lsb_batch_tune_get_op(int(op), ctypes.byref(cfg)))
+    return cfg.as_dict()
+
+
+def tune_set_op(op: int, block: int, unroll: int, blocks_per_cu: int, nontemporal: int) -> None:
+    cfg = LaunchCfg(block, unroll, blocks_per_cu, nontemporal, 0)
+    check(lib().lsb_batch_tune_set_op(int(op), ctypes.byref(cfg)))
+
+
+def set_tile_vectors(tile_vectors: int) -> None:
+    """Change the tile size only (both launch shapes stay)."""
+    state = tune_state()
+    tune_restore((state[0], state[1], int(tile_vectors)))
+
+
+def tune_state():
+    """Both launch shapes and the tile size, for tune_restore."""
+    return tune_get_op(OP_EMBED), tune_get_op(OP_EXTRACT), tune_get()[1]
+
+
+def tune_restore(state) -> None:
+    emb, ext, tv = state
+    tune_set(emb["block"], emb["unroll"], emb["blocks_per_cu"], emb["nontemporal"], tv)
+    tune_set_op(OP_EXTRACT, ext["block"], ext["unroll"], ext["blocks_per_cu"], ext["nontemporal"])
+
+
 __all__ = ["Plan", "make_jobs", "align_up", "run_static", "JOB_DTYPE", "JOB_RAW", "OP_EMBED", "OP_EXTRACT", "OP_MIXED",
-           "STATIC_MAX_JOBS", "tune_get", "tune_set"]
+           "STATIC_MAX_JOBS", "tune_get", "tune_set", "tune_get_op", "tune_set_op", "tune_state", "tune_restore",
+           "set_tile_vectors"]

@@ -26,11 +26,15 @@
 
 namespace lsb {
 
-// Prologue: one wave per job writes the job's status (and decoded length).
+// Prologue: one wave per job writes the job's status (and decoded length);
+// thread 0 resets the persistent kernel's tile counter, which the kernel
+// after it reads (stream order), so a run whose job table is already on the
+// device needs no upload.
 __global__ void __launch_bounds__(256)
     lsb_batch_prologue(const PlanHeader *hdr, const DevJob *jobs, const uint8_t *stego_arena, uint32_t *len_dev,
                        int32_t *status_dev) {
     const uint32_t lane = threadIdx.x & 63u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) const_cast<PlanHeader *>(hdr)->next_tile = 0;
     const uint64_t n_jobs = hdr->n_jobs;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
@@ -60,10 +64,19 @@ static BatchFn batch_fn(int unroll, int nt, int cls, bool raw) {
     return raw ? batch_fn_raw(unroll, nt, cls) : batch_fn_for<false>(unroll, nt, cls);
 }
 
-// Batched-kernel configuration (global, read at each run).
+// Batched-kernel configuration (global, read at each run): the launch shape
+// of plans with embed jobs (entry 0) and of extract-only plans (entry 1),
+// and the tile size of both.
 static std::mutex g_batch_mu;
-static lsb_launch_cfg g_batch_cfg = {256, 2, 8, 0, 0};
-static int64_t g_tile_vectors = 8192;
+static lsb_launch_cfg g_batch_cfg[2] = {{1024, 2, 2, 1, 0}, {1024, 4, 2, 1, 0}};
+static int64_t g_tile_vectors = 4096;
+
+// Launch shape of a plan: extract-only plans have their own entry.
+static lsb_launch_cfg batch_cfg_for(bool has_embed, bool has_extract, int64_t *tv) {
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    *tv = g_tile_vectors;
+    return g_batch_cfg[has_extract && !has_embed ? 1 : 0];
+}
 
 }  // namespace lsb
 
@@ -86,6 +99,7 @@ struct lsb_plan {
     hipEvent_t done = nullptr;  // recorded after each run
     hipStream_t last_stream = nullptr;  // stream of the last run
     bool ran = false;
+    bool table_dirty = true;  // the host table changed since the last upload
     // graph state
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -409,6 +423,7 @@ int lsb_plan_update(lsb_plan *p, const lsb_job *jobs, int n_jobs) {
     p->cls = t.cls;
     p->tile_vectors = tv;
     p->used_bytes = t.used_bytes;
+    p->table_dirty = true;
     return LSB_OK;
 }
 
@@ -469,13 +484,8 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
     const hipError_t de = hipGetDevice(&dev);
     if (de != hipSuccess) return hip_fail(de, "hipGetDevice");
     if (dev != p->device) return fail(LSB_E_ARG, "lsb_plan_run: plan belongs to device %d, current is %d", p->device, dev);
-    lsb_launch_cfg cfg;
     int64_t tv;
-    {
-        std::lock_guard<std::mutex> g(g_batch_mu);
-        cfg = g_batch_cfg;
-        tv = g_tile_vectors;
-    }
+    const lsb_launch_cfg cfg = batch_cfg_for(p->has_embed, p->has_extract, &tv);
     if (tv != p->tile_vectors) return fail(LSB_E_ARG, "lsb_plan_run: tile size changed since lsb_plan_update");
     // a different kernel (shape or job class) cannot be swapped into the
     // executable graph: rebuild it
@@ -509,6 +519,10 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
         e = hipStreamWaitEvent((hipStream_t)stream, p->done, 0);
         if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent(plan)");
     }
+    // upload the job table only when it changed since the last upload (the
+    // prologue resets the tile counter either way)
+    e = hipGraphNodeSetEnabled(p->exec, p->copy_node, p->table_dirty ? 1 : 0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphNodeSetEnabled(table upload)");
     e = hipGraphLaunch(p->exec, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     e = hipEventRecord(p->done, (hipStream_t)stream);
@@ -519,6 +533,7 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
         return hip_fail(e, "hipEventRecord(plan)");
     }
     p->ran = true;
+    p->table_dirty = false;
     p->last_stream = (hipStream_t)stream;
     return LSB_OK;
 }
@@ -571,13 +586,7 @@ int lsb_batch_run_static(const lsb_job *jobs, int n_jobs, int op, const uint8_t 
         return fail(LSB_E_ARG, "lsb_batch_run_static: arena base pointers must be 256-byte aligned");
     int rc = validate_jobs(jobs, n_jobs, op);
     if (rc != LSB_OK) return rc;
-    lsb_launch_cfg cfg;
-    int64_t tv;
-    {
-        std::lock_guard<std::mutex> g(g_batch_mu);
-        cfg = g_batch_cfg;
-        tv = g_tile_vectors;
-    }
+    const int64_t tv = batch_tile_vectors();
     hipStream_t st = (hipStream_t)stream;
     // One host staging table for all devices: filled and uploaded under the
     // lock.  An upload from pageable memory has read the source when
@@ -587,6 +596,9 @@ int lsb_batch_run_static(const lsb_job *jobs, int n_jobs, int op, const uint8_t 
     rc = static_table(&table);
     if (rc != LSB_OK) return rc;
     const TableInfo t = fill_table(jobs, n_jobs, op, tv, g_static_host);
+    int64_t tv_now;
+    const lsb_launch_cfg cfg = batch_cfg_for(t.has_embed, t.has_extract, &tv_now);
+    if (tv_now != tv) return fail(LSB_E_ARG, "lsb_batch_run_static: tile size changed during the call");
     if (t.has_extract && !len_dev) return fail(LSB_E_ARG, "lsb_batch_run_static: extract jobs need len_dev");
     if (t.has_embed && !cover_arena) return fail(LSB_E_ARG, "lsb_batch_run_static: embed jobs need a cover arena");
     hipError_t e = hipMemcpyAsync(table, g_static_host, t.used_bytes, hipMemcpyHostToDevice, st);
@@ -606,18 +618,40 @@ int lsb_batch_run_static(const lsb_job *jobs, int n_jobs, int op, const uint8_t 
 
 int lsb_batch_tune_get(lsb_launch_cfg *cfg, int64_t *tile_vectors) {
     std::lock_guard<std::mutex> g(g_batch_mu);
-    if (cfg) *cfg = g_batch_cfg;
+    if (cfg) *cfg = g_batch_cfg[0];
     if (tile_vectors) *tile_vectors = g_tile_vectors;
     return LSB_OK;
 }
 
+static bool batch_cfg_valid(const lsb_launch_cfg *cfg) {
+    // one wave of every block hands out tiles, the others stream them
+    return cfg && cfg_valid(*cfg) && cfg->block >= 128;
+}
+
 int lsb_batch_tune_set(const lsb_launch_cfg *cfg, int64_t tile_vectors) {
-    if (!cfg || !cfg_valid(*cfg)) return fail(LSB_E_ARG, "lsb_batch_tune_set: invalid configuration");
+    if (!batch_cfg_valid(cfg))
+        return fail(LSB_E_ARG, "lsb_batch_tune_set: invalid configuration (blocks need at least 128 threads)");
     if (tile_vectors < 64 || tile_vectors > (1ll << 30) || tile_vectors % 64)
         return fail(LSB_E_ARG, "lsb_batch_tune_set: tile_vectors must be a multiple of 64 in [64, 2^30]");
     std::lock_guard<std::mutex> g(g_batch_mu);
-    g_batch_cfg = *cfg;
+    g_batch_cfg[0] = g_batch_cfg[1] = *cfg;
     g_tile_vectors = tile_vectors;
+    return LSB_OK;
+}
+
+int lsb_batch_tune_get_op(int op, lsb_launch_cfg *cfg) {
+    if ((op != LSB_OP_EMBED && op != LSB_OP_EXTRACT) || !cfg) return fail(LSB_E_ARG, "lsb_batch_tune_get_op: bad op or null");
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    *cfg = g_batch_cfg[op == LSB_OP_EXTRACT ? 1 : 0];
+    return LSB_OK;
+}
+
+int lsb_batch_tune_set_op(int op, const lsb_launch_cfg *cfg) {
+    if (op != LSB_OP_EMBED && op != LSB_OP_EXTRACT) return fail(LSB_E_ARG, "lsb_batch_tune_set_op: op=%d", op);
+    if (!batch_cfg_valid(cfg))
+        return fail(LSB_E_ARG, "lsb_batch_tune_set_op: invalid configuration (blocks need at least 128 threads)");
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    g_batch_cfg[op == LSB_OP_EXTRACT ? 1 : 0] = *cfg;
     return LSB_OK;
 }
 

@@ -151,56 +151,156 @@ constexpr int batch_min_waves() {
     else return 4;
 }
 
-// Persistent kernel.  Every wave of a block works on the block's tile; the
-// job of a tile is found by a forward search over the tile prefix that 64
-// lanes do in one step (jobs only move forward as the tile id grows).
+// Tile hand-off inside a block.  Wave 0 is the block's producer and does no
+// streaming itself: it takes the next tile id from the plan's counter,
+// resolves the tile's job (forward search over the tile prefix, 64 jobs per
+// ballot; jobs only move forward as the tile id grows), reads the job record
+// and the job's device status, and publishes all of it in a slot of a
+// two-slot LDS ring.  The other waves (the workers) read their next tile
+// from the ring when they finish the current one, so they never wait for
+// each other at a tile boundary, and the latency of the counter, the search
+// and the record reads is spent by the producer while the workers stream.
+// The producer publishes tile m + 1 once every worker has taken tile m (the
+// slot it overwrites was read before that), so a block holds at most one
+// tile beyond the one its slowest worker is on.  Every wait is
+// bounded (kSpinLimit polls): a wave whose partner never answers gives up
+// instead of hanging the device (its tiles are then left undone).
+constexpr int kRing = 2;
+constexpr uint32_t kSpinLimit = 1u << 26;
+
+struct TileSlot {
+    DevJob job;       // the tile's job record
+    uint64_t tile;    // global tile id; >= total ends the block
+    uint32_t len;     // header extract: decoded message length
+    uint32_t run;     // 1: the job has work (status OK)
+};
+
+// Ordering of the hand-off.  The LDS instructions of one wave execute in
+// the order they are issued, and a wave observes another wave's LDS write
+// once it has executed.  So the ring needs only relaxed LDS accesses kept in
+// program order by compiler barriers: the producer writes a slot, then its
+// sequence number; a worker reads the sequence number, then the slot, then
+// counts itself as a reader.  (Release/acquire atomics would also order the
+// waves' global memory traffic: a worker would wait for its previous tile's
+// stores to complete at every tile boundary.)
+__device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
+
+__device__ __forceinline__ uint32_t lds_read(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void lds_write(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Wait (wave-uniform) until *p == want; false if the limit ran out.
+__device__ __forceinline__ bool lds_wait_eq(const uint32_t *p, uint32_t want) {
+    for (uint32_t i = 0; i < kSpinLimit; ++i) {
+        const uint32_t v = lds_read(p);
+        lds_order();
+        if (v == want) return true;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return false;
+}
+
+__device__ __forceinline__ uint32_t uniform32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    return ((uint64_t)uniform32((uint32_t)(v >> 32)) << 32) | uniform32((uint32_t)v);
+}
+
+// Persistent kernel: tiles come from one counter in arrival order, so the
+// tiles in flight at any moment are neighbours in the arenas (a static b,
+// b + G, ... order lets blocks drift apart over the run).  Blocks have at
+// least two waves (one producer, at least one worker).
 template <int UNR, bool NT, int CLS, bool RAW>
 __global__ void __launch_bounds__(1024, (batch_min_waves<UNR, CLS, RAW>()))
     lsb_batch_kernel(const PlanHeader *hdr, const DevJob *jobs, const uint8_t *cover_arena, uint8_t *stego_arena,
                      uint8_t *msg_arena, const uint32_t *len_dev, const int32_t *status_dev) {
-    // Blocks take tiles from one counter in arrival order, so the tiles in
-    // flight at any moment are neighbours in the arenas (a static b, b + G,
-    // ... order lets blocks drift apart over the run).  Thread 0 requests the
-    // next tile while the block works on the current one; the answer goes
-    // through a double-buffered LDS slot, read after the tile's barrier.
-    __shared__ uint64_t grabbed[2];
-    unsigned long long *counter = (unsigned long long *)&const_cast<PlanHeader *>(hdr)->next_tile;
+    __shared__ TileSlot ring[kRing];
+    __shared__ uint32_t seq[kRing];      // iteration whose tile the slot holds
+    __shared__ uint32_t readers[kRing];  // workers that have read the slot's current content
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
-    const uint32_t n_waves = blockDim.x >> 6;
-    const uint64_t n_jobs = hdr->n_jobs;
+    const uint32_t workers = (blockDim.x >> 6) - 1;
     const uint64_t total = hdr->total_tiles;
-    const uint64_t tv_embed = hdr->tile_vectors;
-    if (threadIdx.x == 0) grabbed[0] = atomicAdd(counter, 1ull);
+    if (threadIdx.x < kRing) {
+        seq[threadIdx.x] = ~0u;
+        readers[threadIdx.x] = workers;  // free
+    }
     __syncthreads();
-    uint64_t tile = grabbed[0];
-    uint64_t j = 0;
-    for (uint32_t it = 1; tile < total; ++it) {  // `tile` is block-uniform
-        if (threadIdx.x == 0) grabbed[it & 1u] = atomicAdd(counter, 1ull);
-        // largest j with jobs[j].tile_begin <= tile (entry n_jobs holds total > tile);
-        // a block's tiles only grow, so the search runs forward
-        for (;;) {
-            const uint64_t idx = j + 1 + lane;
-            const uint64_t tb = idx <= n_jobs ? jobs[idx].tile_begin : ~0ull;
-            const uint64_t below = __ballot(tb <= tile);
-            const uint32_t cnt = (uint32_t)__popcll(below);
-            j += cnt;
-            if (cnt < 64) break;
+
+    if (wave == 0) {
+        // ---- producer
+        unsigned long long *counter = (unsigned long long *)&const_cast<PlanHeader *>(hdr)->next_tile;
+        const uint64_t n_jobs = hdr->n_jobs;
+        uint64_t j = 0;  // job search cursor
+        uint64_t t = 0;
+        if (lane == 0) t = atomicAdd(counter, 1ull);
+        for (uint32_t m = 0;; ++m) {
+            t = uniform64(t);
+            const uint32_t sl = m % kRing;
+            uint32_t run = 0, len = 0;
+            if (t < total) {
+                // largest j with jobs[j].tile_begin <= t (entry n_jobs holds total > t)
+                for (;;) {
+                    const uint64_t idx = j + 1 + lane;
+                    const uint64_t tb = idx <= n_jobs ? jobs[idx].tile_begin : ~0ull;
+                    const uint64_t below = __ballot(tb <= t);
+                    const uint32_t cnt = (uint32_t)__popcll(below);
+                    j += cnt;
+                    if (cnt < 64) break;
+                }
+                j = uniform64(j);
+                run = jobs[j].status == LSB_OK;
+                if (run && jobs[j].op == LSB_OP_EXTRACT && !(RAW && jobs[j].raw)) {
+                    run = status_dev[j] == LSB_OK;
+                    len = len_dev[j];
+                }
+            }
+            // every worker must have taken tile m - 1 (and so every earlier one)
+            if (m && !lds_wait_eq(&readers[(m - 1) % kRing], workers)) return;
+            if (lane == 0) {
+                if (t < total) ring[sl].job = jobs[j];
+                ring[sl].tile = t;
+                ring[sl].len = len;
+                ring[sl].run = run;
+                lds_write(&readers[sl], 0);
+                lds_order();
+                lds_write(&seq[sl], m);
+            }
+            if (t >= total) return;  // the end mark is out
+            if (lane == 0) t = atomicAdd(counter, 1ull);
         }
-        const DevJob J = jobs[j];
-        bool run = J.status == LSB_OK;
-        uint32_t len = 0;
-        if (run && J.op == LSB_OP_EXTRACT && !(RAW && J.raw)) {
-            run = status_dev[j] == LSB_OK;
-            len = len_dev[j];
+    }
+
+    // ---- workers
+    const uint64_t tv_embed = hdr->tile_vectors;
+    for (uint32_t m = 0;; ++m) {
+        const uint32_t sl = m % kRing;
+        if (!lds_wait_eq(&seq[sl], m)) return;
+        // the slot, read into wave-uniform registers
+        const uint64_t tile = uniform64(ring[sl].tile);
+        DevJob J;
+        {
+            const uint32_t *src = reinterpret_cast<const uint32_t *>(&ring[sl].job);
+            uint32_t *dst = reinterpret_cast<uint32_t *>(&J);
+#pragma unroll
+            for (int i = 0; i < (int)(sizeof(DevJob) / 4); ++i) dst[i] = uniform32(src[i]);
         }
-        // an extract tile covers twice the vectors of an embed tile
-        const uint64_t tv = J.op == LSB_OP_EXTRACT ? 2 * tv_embed : tv_embed;
-        if (run)
+        const uint32_t len = uniform32(ring[sl].len);
+        const uint32_t run = uniform32(ring[sl].run);
+        lds_order();
+        if (lane == 0) __hip_atomic_fetch_add(&readers[sl], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (tile >= total) return;
+        if (run) {
+            // an extract tile covers twice the vectors of an embed tile; the
+            // workers' shares of a tile rotate from tile to tile
+            const uint64_t tv = J.op == LSB_OP_EXTRACT ? 2 * tv_embed : tv_embed;
+            const uint32_t w = (wave - 1 + m) % workers;
             run_tile<UNR, NT, CLS, RAW>(J, (tile - J.tile_begin) * tv, tv, cover_arena, stego_arena, msg_arena, len,
-                                   wave, n_waves, lane);
-        __syncthreads();
-        tile = grabbed[it & 1u];
+                                        w, workers, lane);
+        }
     }
 }
 

@@ -108,8 +108,7 @@ def _run_and_check(jobs, order=None, tile_vectors=None, plan=None):
     status = torch.full((len(jobs),), 99, dtype=torch.int32, device=DEV)
     lens = torch.zeros(len(jobs), dtype=torch.int32, device=DEV)
     if tile_vectors is not None:
-        cfg, _ = batch.tune_get()
-        batch.tune_set(cfg["block"], cfg["unroll"], cfg["blocks_per_cu"], cfg["nontemporal"], tile_vectors)
+        batch.set_tile_vectors(tile_vectors)
     own = plan is None
     if own:
         plan = batch.Plan(len(jobs))
@@ -160,11 +159,11 @@ def test_mixed_batch_shuffled(mixed):
 def test_small_tiles(mixed, tv):
     """Tiles of 64 or 1024 vectors put many tile boundaries inside each cover;
     results must not change."""
-    old_cfg, old_tv = batch.tune_get()
+    saved = batch.tune_state()
     try:
         _run_and_check(mixed, tile_vectors=tv)
     finally:
-        batch.tune_set(old_cfg["block"], old_cfg["unroll"], old_cfg["blocks_per_cu"], old_cfg["nontemporal"], old_tv)
+        batch.tune_restore(saved)
 
 
 @pytest.mark.parametrize("ks", [(1, 3), (2, 5, 8)])
@@ -177,8 +176,7 @@ def test_few_class_mixed_plans(ks, restore_tiles):
     jobs = _mixed_batch(48, 2500 + len(ks), ks=ks)
     assert len({(j["op"], j["k"]) for j in jobs}) == 2 * len(ks)
     _run_and_check(jobs, order=inputs.rng(2510).permutation(len(jobs)))
-    cfg, _ = batch.tune_get()
-    batch.tune_set(cfg["block"], cfg["unroll"], cfg["blocks_per_cu"], cfg["nontemporal"], 64)
+    batch.set_tile_vectors(64)
     _run_and_check(jobs, order=inputs.rng(2511).permutation(len(jobs)))
     # one plan, job lists of one class, two classes, then all of them (graphs rebuilt)
     plan = batch.Plan(len(jobs))
@@ -198,16 +196,15 @@ def test_extract_plan_of_every_k(restore_tiles):
     assert len({j["k"] for j in jobs}) == 8
     assert {E_HEADER, E_BUFFER, OK} <= {j["status"] for j in jobs}
     _run_and_check(jobs, order=inputs.rng(2601).permutation(len(jobs)))
-    cfg, _ = batch.tune_get()
-    batch.tune_set(cfg["block"], cfg["unroll"], cfg["blocks_per_cu"], cfg["nontemporal"], 64)
+    batch.set_tile_vectors(64)
     _run_and_check(jobs)
 
 
 @pytest.fixture
 def restore_tiles():
-    old_cfg, old_tv = batch.tune_get()
+    saved = batch.tune_state()
     yield
-    batch.tune_set(old_cfg["block"], old_cfg["unroll"], old_cfg["blocks_per_cu"], old_cfg["nontemporal"], old_tv)
+    batch.tune_restore(saved)
 
 
 def test_plan_reuse_across_job_lists(mixed):
@@ -245,11 +242,11 @@ def test_uniform_class_plans(k, op):
     that pair only: oracle parity with invalid jobs, default and tiny tiles."""
     jobs = _mixed_batch(30, 2300 + 10 * k + op, k_fixed=k, op_fixed=op)
     _run_and_check(jobs)
-    old_cfg, old_tv = batch.tune_get()
+    saved = batch.tune_state()
     try:
         _run_and_check(jobs, tile_vectors=64)
     finally:
-        batch.tune_set(old_cfg["block"], old_cfg["unroll"], old_cfg["blocks_per_cu"], old_cfg["nontemporal"], old_tv)
+        batch.tune_restore(saved)
 
 
 def test_plan_kinds_and_named_calls():

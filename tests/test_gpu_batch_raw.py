@@ -55,15 +55,14 @@ def _frames_layout(clips):
 
 
 def _set_tiles(tv):
-    cfg, _ = batch.tune_get()
-    batch.tune_set(cfg["block"], cfg["unroll"], cfg["blocks_per_cu"], cfg["nontemporal"], tv)
+    batch.set_tile_vectors(tv)
 
 
 @pytest.fixture
 def restore_tiles():
-    old_cfg, old_tv = batch.tune_get()
+    saved = batch.tune_state()
     yield
-    batch.tune_set(old_cfg["block"], old_cfg["unroll"], old_cfg["blocks_per_cu"], old_cfg["nontemporal"], old_tv)
+    batch.tune_restore(saved)
 
 
 def _embed_extract_clips(specs, seed, plan_op, order_seed=None):
