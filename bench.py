@@ -151,23 +151,49 @@ def cpu_baseline(cover_np, msgs, min_seconds=10.0, max_steps=4):
 
 
 def cpu_model():
+    """The host CPU's model name as /proc/cpuinfo states it (lscpu reads the
+    same field), plus its family/model/stepping numbers."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if ":" not in line:
+                    if info:
+                        break  # first processor only
+                    continue
+                key, val = (x.strip() for x in line.split(":", 1))
+                if key in ("model name", "cpu family", "model", "stepping") and key not in info:
+                    info[key] = val
     except OSError:
         pass
-    return None
+    if not info:
+        return None
+    return "%s (family %s, model %s, stepping %s)" % (info.get("model name", "?"), info.get("cpu family", "?"),
+                                                     info.get("model", "?"), info.get("stepping", "?"))
 
 
-def cpu_baseline_threads(cover_np, msgs, threads):
-    """The same oracle on `threads` host cores: the cover is cut into shards
-    at multiples of 8 bytes (so every shard's first stream bit k*t0 is byte
+def host_cpus():
+    """Cores of the host and the share this process may use: os.cpu_count()
+    counts every logical CPU of the machine, the affinity mask the ones this
+    process is allowed to run on; a one-GPU share of the GPU host is at most
+    16 cores, which is what the threaded oracle uses."""
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count() or 1
+    return {"cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(), "affinity_cpus": allowed,
+            "cpu_share": max(1, min(16, allowed))}
+
+
+def cpu_baseline_threads(cover_np, msgs, threads, min_seconds=1.5, max_steps=4):
+    """The oracle on `threads` host cores: the cover is cut into shards at
+    multiples of 8 bytes (so every shard's first stream bit k*t0 is byte
     aligned at every k), and each thread embeds and then extracts its shard
-    as a raw slice of the stream.  Same work and byte counts as the
-    single-thread leg; the stream (header + message) is assembled in the
-    timed region."""
+    as a raw slice of the stream with the oracle's raw-slice functions as
+    they stand.  Whole steps (same work and byte counts as the single-thread
+    leg) repeat until `min_seconds` of wall time (about 24 s of CPU work on
+    16 cores), at most `max_steps`; the stream (header + message) is
+    assembled in the timed region."""
     from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
@@ -180,31 +206,34 @@ def cpu_baseline_threads(cover_np, msgs, threads):
     shards = [(bounds[i], bounds[i + 1]) for i in range(threads) if bounds[i + 1] > bounds[i]]
     total = 0
     outs = {}
+    steps = 0
     with ThreadPoolExecutor(len(shards)) as pool:
         t0 = time.perf_counter()
-        for k in KS:
-            stream = np.frombuffer(stream_of(msgs[k].tobytes()), np.uint8)
-            bits = 8 * stream.size
-            out = np.zeros(stream.size, np.uint8)
+        while steps < max_steps and (steps == 0 or time.perf_counter() - t0 < min_seconds):
+            for k in KS:
+                stream = np.frombuffer(stream_of(msgs[k].tobytes()), np.uint8)
+                bits = 8 * stream.size
+                out = np.zeros(stream.size, np.uint8)
 
-            def one(ab, k=k, stream=stream, bits=bits, out=out):
-                a, b = ab
-                rc, stego = oracle.embed_raw(cover_np[a:b], a, stream, bits, k)
-                assert rc == 0
-                rc, _ = oracle.extract_raw(stego, a, bits, k, stream_out=out)
-                assert rc == 0
+                def one(ab, k=k, stream=stream, bits=bits, out=out):
+                    a, b = ab
+                    rc, stego = oracle.embed_raw(cover_np[a:b], a, stream, bits, k)
+                    assert rc == 0
+                    rc, _ = oracle.extract_raw(stego, a, bits, k, stream_out=out)
+                    assert rc == 0
 
-            list(pool.map(one, shards))
-            outs[k] = out
-            total += embed_bytes(n, msgs[k].size) + extract_bytes(n, msgs[k].size, k)
+                list(pool.map(one, shards))
+                outs[k] = out
+                total += embed_bytes(n, msgs[k].size) + extract_bytes(n, msgs[k].size, k)
+            steps += 1
         dt = time.perf_counter() - t0
     for k in KS:  # the decoded header and message must be the input's
         ln = int.from_bytes(outs[k][:4].tobytes(), "big")
         assert ln == msgs[k].size and np.array_equal(outs[k][4:], msgs[k]), k
     return {"value": round(total / dt / 1e9, 4), "unit": "GB/s", "cores": len(shards), "kind": "oracle",
-            "sample": "one full step as the single-thread leg, the cover cut into %d shards of about %d MB "
-                      "run as raw slices on %d threads (%.2f s)" % (len(shards), n // len(shards) >> 20,
-                                                                     len(shards), dt)}
+            "sample": "%d full step%s (embed+extract at k=1,2,4 of the 8192x8192x3 cover on host buffers), the "
+                      "cover cut into %d shards of about %d MB run as raw slices on %d threads (%.2f s wall)"
+                      % (steps, "" if steps == 1 else "s", len(shards), n // len(shards) >> 20, len(shards), dt)}
 
 
 def bench_batched(api, batch, dev, log_fn, reps=3):
@@ -669,26 +698,51 @@ def bench_video(api, lib_handle, dev, log_fn, frames=600, h=1080, w=1920):
     return res
 
 
-def bench_serving(api, serve, dev, pool, log_fn, rates=(2000.0, 10000.0, 50000.0), seconds=1.0,
+def bench_serving(api, serve, dev, pool, log_fn, rates=(2000.0, 10000.0, 50000.0), requests=200000,
                   budget=64 << 30):
     """Open-loop Poisson request streams over the device-resident 4096-cover
-    pool, 50/50 embed/extract, admission by a 64 GB HBM budget."""
+    pool, `requests` requests per rate (200,000: 100 s at 2k req/s, 20 s at
+    10k, 4 s at 50k), 50/50 embed/extract, admission by a 64 GB HBM budget.
+    Two labelled runs press the budget: one where embeds outnumber extracts
+    (30 % extracts), so resident stego buffers pile up past the budget and
+    the oldest are evicted; one whose budget (1.5 GB) is below what the
+    requests in flight need at 50k req/s, so admission stalls."""
     import torch
 
     wl, cover, msg = pool
     arena = torch.empty(budget, dtype=torch.uint8, device=dev)
     out = {}
-    for rate in rates:
-        count = int(rate * seconds)
-        req, _ = serve.poisson_requests(wl, rate, count, seed=501)
-        res, st = serve.serve(arena, cover, msg, req, max_batch=256, n_slots=4, keep_outputs=False)
+
+    def row(st, count, res, **extra):
         ok = int((res["status"] == 0).sum())
-        out["%dk" % int(rate / 1000)] = {
-            "requests": count, "ok": ok, "GBps": round(st["gbps"], 1), "p50_ms": round(st["p50_ms"], 3),
-            "p99_ms": round(st["p99_ms"], 3), "max_ms": round(st["max_ms"], 3),
-            "mean_batch": round(st["mean_batch"], 2), "launches": st["launches"], "evictions": st["evictions"],
-            "stalls": st["admission_stalls"], "peak_budget_GB": round(st["peak_arena_bytes"] / 1e9, 2)}
+        r = {"requests": count, "ok": ok, "GBps": round(st["gbps"], 1), "p50_ms": round(st["p50_ms"], 3),
+             "p99_ms": round(st["p99_ms"], 3), "max_ms": round(st["max_ms"], 3),
+             "mean_batch": round(st["mean_batch"], 2), "launches": st["launches"], "evictions": st["evictions"],
+             "stalls": st["admission_stalls"], "rejected": st["rejected"],
+             "peak_budget_GB": round(st["peak_arena_bytes"] / 1e9, 2), "makespan_s": round(st["makespan_s"], 3)}
+        r.update(extra)
+        return r
+
+    for rate in rates:
+        count = int(requests)
+        req, _ = serve.poisson_requests(wl, rate, count, seed=501)
+        log_fn("serving %d requests at %d req/s (%.0f s of arrivals) ..." % (count, rate, count / rate))
+        res, st = serve.serve(arena, cover, msg, req, max_batch=256, n_slots=4, keep_outputs=False)
+        out["%dk" % int(rate / 1000)] = row(st, count, res, budget_GB=round(budget / 1e9, 1), extract_frac=0.5)
         log_fn("serving %d req/s: %s" % (rate, out["%dk" % int(rate / 1000)]))
+    # the budget under pressure
+    count = min(int(requests), 100000)
+    req, _ = serve.poisson_requests(wl, 10000.0, count, seed=502, extract_frac=0.3)
+    log_fn("serving under eviction pressure ...")
+    res, st = serve.serve(arena, cover, msg, req, max_batch=256, n_slots=4, keep_outputs=False)
+    out["pressured_evict_10k"] = row(st, count, res, budget_GB=round(budget / 1e9, 1), extract_frac=0.3)
+    log_fn("pressured (evictions): %s" % out["pressured_evict_10k"])
+    small = int(1.5e9)
+    req, _ = serve.poisson_requests(wl, 50000.0, count, seed=503)
+    log_fn("serving with a budget below the requests in flight ...")
+    res, st = serve.serve(arena[:small], cover, msg, req, max_batch=256, n_slots=4, keep_outputs=False)
+    out["pressured_stall_50k"] = row(st, count, res, budget_GB=round(small / 1e9, 2), extract_frac=0.5)
+    log_fn("pressured (stalls): %s" % out["pressured_stall_50k"])
     del arena
     return out
 
@@ -702,10 +756,11 @@ def main():
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-cover batched comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving streams")
-    ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--events", choices=("dominant", "all"), default="dominant",
                     help="launches timed with kernel-bound events inside the timed region: the dominant "
-                         "k=1 embed only (others timed in a short pass afterwards), or all six")
+                         "k=4 embed only (others timed in a short pass afterwards), or all six")
+    ap.add_argument("--serve-requests", type=int, default=200000,
+                    help="requests per arrival rate of the serving streams")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this implementation has no multi-GPU path (each GPU would take "
@@ -764,7 +819,10 @@ def main():
 
     # timed region: K steps, per-launch HIP events on the launch stream
     all_keys = [(op, k) for op in ("embed", "extract") for k in KS]
-    timed_keys = all_keys if args.events == "all" else [("embed", 1)]
+    # the dominant launch: the k = 4 embed moves the most bytes of the step
+    # (2n + n/2 + 4) and takes the largest share of it
+    dominant = ("embed", 4)
+    timed_keys = all_keys if args.events == "all" else [dominant]
 
     def make_events(steps, keys):
         ev = [{key: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for key in keys}
@@ -822,13 +880,15 @@ def main():
                                    "us_mean": round(statistics.fmean(ms) * 1e3, 2),
                                    "GBps_median": round(b / (med * 1e-3) / 1e9, 1)}
     value = step_bytes * args.steps / wall / 1e9
-    dom = per["embed_k1"]
+    dkey = "%s_k%d" % dominant
+    dom = per[dkey]
     achieved = dom["bytes"] / (dom["us_mean"] * 1e-6) / 1e9
-    kernel = launch_kernel_name(api, "embed", 1, n)
-    traffic = stored_traffic(kernel)
+    kernel = launch_kernel_name(api, dominant[0], dominant[1], n)
+    traffic = stored_launch_traffic(dkey, kernel)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": kernel + " (k=1 embed, 8192x8192x3 cover, full-capacity message)",
+                "kernel": kernel + " (k=4 embed, 8192x8192x3 cover, full-capacity message: the step's longest "
+                                   "launch)",
                 "algorithmic_bytes_per_launch": dom["bytes"], "launch_us_mean": dom["us_mean"]}
 
     # every launch of the step against the same peak, with its share of the step
@@ -842,6 +902,8 @@ def main():
                           "traffic": stored_launch_traffic(key, name), "us_mean": per[key]["us_mean"],
                           "share_of_step": round(per[key]["us_mean"] / step_us, 4)}
 
+    longest = max(by_launch, key=lambda key: by_launch[key]["share_of_step"])
+    roofline["dominant_by_share"] = longest  # the launch with the largest share of the measured step
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 4), "higher_is_better": True,
@@ -929,16 +991,18 @@ def main():
         log("batched (4096 uneven covers) ...")
         result["batched"], pool = bench_batched(api, batch, dev, log)
         if not args.no_serving:
-            result["serving"] = bench_serving(api, serve, dev, pool, log, seconds=args.serve_seconds)
+            result["serving"] = bench_serving(api, serve, dev, pool, log, requests=args.serve_requests)
         del pool
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
+        host = host_cpus()
+        threads = host["cpu_share"]
+        log("timing the CPU oracle on whole steps, %d threads ..." % threads)
+        result["cpu_baseline"] = cpu_baseline_threads(cover_np, msgs_np, threads)
+        result["cpu_baseline"].update(host)
         log("timing the CPU oracle on whole steps (at least 10 s), one thread ...")
-        result["cpu_baseline"] = cpu_baseline(cover_np, msgs_np)
-        result["cpu_baseline"]["cpu_model"] = cpu_model()
-        threads = max(1, min(16, os.cpu_count() or 1))
-        log("timing the CPU oracle on one step, %d threads ..." % threads)
-        result["cpu_baseline_threads"] = cpu_baseline_threads(cover_np, msgs_np, threads)
+        result["cpu_baseline_single"] = cpu_baseline(cover_np, msgs_np)
+        result["cpu_baseline_single"].update(host)
     print(json.dumps(result), flush=True)
 
 

@@ -332,13 +332,24 @@ def main():
     ap.add_argument("--batch", action="store_true", help="also sweep the batched kernel")
     ap.add_argument("--batch-only", action="store_true",
                     help="sweep the batched kernel only; the stored plain-kernel entries stay")
+    ap.add_argument("--sequence-only", action="store_true",
+                    help="re-choose the large-image workload's six launch shapes inside their sequence only")
     ap.add_argument("--out", default=TABLE)
     args = ap.parse_args()
     import torch
 
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    if args.sequence_only:
+        with open(TABLE) as f:
+            table = json.load(f)
+        seq = {(e["op"], e["k"], e["bucket"]): e for e in tune_sequence(log=log)}
+        table["entries"] = [seq.get((e["op"], e["k"], e["bucket"]), e) for e in table["entries"]]
+        with open(args.out, "w") as f:
+            json.dump(table, f, indent=1)
+        log("wrote", args.out)
+        return
     if args.batch_only:
-        with open(args.out) as f:
+        with open(TABLE) as f:
             table = json.load(f)
         table["batch"], table["batch_sweep"] = tune_batch(log=log)
         with open(args.out, "w") as f:

@@ -58,8 +58,20 @@ def test_threaded_oracle_leg():
     cover = np.random.default_rng(7).integers(0, 256, n, dtype=np.uint8)
     msgs = {k: np.random.default_rng(10 + k).integers(0, 256, oracle.capacity(n, k), dtype=np.uint8)
             for k in bench.KS}
-    r = bench.cpu_baseline_threads(cover, msgs, 5)
+    r = bench.cpu_baseline_threads(cover, msgs, 5, min_seconds=0.0)
     assert r["kind"] == "oracle" and r["cores"] == 5 and r["value"] > 0 and r["unit"] == "GB/s"
+    assert r["sample"].startswith("1 full step ")
+    many = bench.cpu_baseline_threads(cover, msgs, 3, min_seconds=1e9, max_steps=2)
+    assert many["sample"].startswith("2 full steps ") and many["cores"] == 3
+
+
+def test_host_cpus_reported():
+    """The baseline states the host's CPU count, the cores this process may
+    use and the share the threaded oracle takes (at most 16)."""
+    h = bench.host_cpus()
+    assert h["os_cpu_count"] == os.cpu_count()
+    assert 1 <= h["cpu_share"] <= min(16, h["affinity_cpus"])
+    assert h["cpu_model"] is None or "family" in h["cpu_model"]
 
 
 def test_single_thread_oracle_leg_repeats_to_its_time_floor():
