@@ -350,6 +350,34 @@ def bench_small_image(api, lib_handle, dev, reps=50):
     for name, pairs in ev.items():
         res[name + "_kernel_us"] = round(statistics.median(a.elapsed_time(b) * 1e3 for a, b in pairs), 2)
     res["roundtrip_us"] = round(statistics.median(rt), 1)
+    # the same round trip (embed + extract_sync) issued three ways: through
+    # the Python API (argument checks, torch tensors), as bare ctypes calls on
+    # raw pointers, and from C++ inside the library (lsb_roundtrip_latency)
+    import ctypes
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    cp, sp_, mp, op = cover.data_ptr(), stego.data_ptr(), msg.data_ptr(), out.data_ptr()
+    got = ctypes.c_uint32(0)
+    raw = []
+    for r in range(reps + 5):
+        t0 = time.perf_counter()
+        lib_handle.lsb_embed(cp, sp_, n, mp, 32768, 1, sp)
+        lib_handle.lsb_extract_sync(sp_, n, 1, op, 32768, ctypes.byref(got), sp)
+        if r >= 5:
+            raw.append((time.perf_counter() - t0) * 1e6)
+    assert got.value == 32768
+    py_sync = []
+    for r in range(reps + 5):
+        t0 = time.perf_counter()
+        api.embed(cover, msg, 1, out=stego)
+        api.extract_sync(stego, 1, out=out)
+        if r >= 5:
+            py_sync.append((time.perf_counter() - t0) * 1e6)
+    med, mn = ctypes.c_double(), ctypes.c_double()
+    rc = lib_handle.lsb_roundtrip_latency(cp, sp_, n, mp, 32768, 1, op, reps, ctypes.byref(med), ctypes.byref(mn), sp)
+    assert rc == 0, rc
+    res["roundtrip_sync_us"] = {"python_api": round(statistics.median(py_sync), 1),
+                                "ctypes_raw": round(statistics.median(raw), 1),
+                                "c_library": round(med.value, 1), "c_library_min": round(mn.value, 1)}
     return res
 
 
@@ -705,7 +733,7 @@ def bench_serving(api, serve, dev, pool, log_fn, rates=(2000.0, 10000.0, 50000.0
     10k, 4 s at 50k), 50/50 embed/extract, admission by a 64 GB HBM budget.
     Two labelled runs press the budget: one where embeds outnumber extracts
     (30 % extracts), so resident stego buffers pile up past the budget and
-    the oldest are evicted; one whose budget (1.5 GB) is below what the
+    the oldest are evicted; one whose budget (192 MiB) is below what the
     requests in flight need at 50k req/s, so admission stalls."""
     import torch
 
@@ -737,7 +765,9 @@ def bench_serving(api, serve, dev, pool, log_fn, rates=(2000.0, 10000.0, 50000.0
     res, st = serve.serve(arena, cover, msg, req, max_batch=256, n_slots=4, keep_outputs=False)
     out["pressured_evict_10k"] = row(st, count, res, budget_GB=round(budget / 1e9, 1), extract_frac=0.3)
     log_fn("pressured (evictions): %s" % out["pressured_evict_10k"])
-    small = int(1.5e9)
+    # room for three of the largest covers (4096 x 4096 x 3 = 50 MB): the
+    # outputs of the requests in flight at 50k req/s overrun it at times
+    small = 192 << 20
     req, _ = serve.poisson_requests(wl, 50000.0, count, seed=503)
     log_fn("serving with a budget below the requests in flight ...")
     res, st = serve.serve(arena[:small], cover, msg, req, max_batch=256, n_slots=4, keep_outputs=False)

@@ -507,6 +507,19 @@ int lsb_serve_simulate(const lsb_server_cfg *cfg, const lsb_request *requests, i
                        lsb_result *results, lsb_serve_stats *stats, double launch_us,
                        double device_gbps);
 
+/* Measurement support: the host-observed latency of `reps` round trips
+ * lsb_embed(cover -> stego) + lsb_extract_sync(stego -> msg_out), issued
+ * from C++ on `stream` (each round trip ends with the synchronisation of
+ * lsb_extract_sync), so that the launch and synchronisation cost of the
+ * library can be told apart from the cost of a binding above it.  Median and
+ * minimum microseconds per round trip.  Arguments as for the two calls
+ * (msg_out holds len bytes); LSB_E_HEADER if a round trip decodes another
+ * length; LSB_E_ARG for reps outside 1..100000. */
+int lsb_roundtrip_latency(const uint8_t *cover, uint8_t *stego, uint64_t n,
+                          const uint8_t *msg, uint32_t len, int k,
+                          uint8_t *msg_out, int reps, double *us_median,
+                          double *us_min, void *stream);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char *lsb_last_error(void);
 

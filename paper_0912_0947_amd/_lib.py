@@ -121,6 +121,8 @@ SIGNATURES = {
                                 ctypes.c_double, ctypes.c_double]),
     "lsb_time_next_launch": (_I, [_P, _P]),
     "lsb_stream_reference": (_I, [_I, _I, _P, _P, _P, _U64, _I, _I, _U32, _P]),
+    "lsb_roundtrip_latency": (_I, [_P, _P, _U64, _P, _U32, _I, _P, _I, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double), _P]),
     "lsb_last_error": (ctypes.c_char_p, []),
     "lsb_version": (ctypes.c_char_p, []),
 }

@@ -16,6 +16,10 @@
 // one writer.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+#include <chrono>
+#include <vector>
+
 #include "lsb_host.hpp"
 
 namespace lsb {
@@ -442,6 +446,27 @@ int lsb_extract_sync(const uint8_t *stego, uint64_t n, int k, uint8_t *msg_out, 
         fail(status, "lsb_extract_sync: %s (decoded length %u)",
              status == LSB_E_HEADER ? "header does not fit the cover" : "output buffer too small", host[0]);
     return status;
+}
+
+int lsb_roundtrip_latency(const uint8_t *cover, uint8_t *stego, uint64_t n, const uint8_t *msg, uint32_t len, int k,
+                          uint8_t *msg_out, int reps, double *us_median, double *us_min, void *stream) {
+    if (reps < 1 || reps > 100000 || !us_median || !us_min) return fail(LSB_E_ARG, "lsb_roundtrip_latency: bad reps");
+    std::vector<double> us;
+    us.reserve((size_t)reps);
+    for (int r = 0; r < reps; ++r) {
+        const auto t0 = std::chrono::steady_clock::now();
+        int rc = lsb_embed(cover, stego, n, msg, len, k, stream);
+        if (rc != LSB_OK) return rc;
+        uint32_t got = 0;
+        rc = lsb_extract_sync(stego, n, k, msg_out, len, &got, stream);
+        if (rc != LSB_OK) return rc;
+        if (got != len) return fail(LSB_E_HEADER, "lsb_roundtrip_latency: decoded %u of %u bytes", got, len);
+        us.push_back(std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count());
+    }
+    std::sort(us.begin(), us.end());
+    *us_median = us[us.size() / 2];
+    *us_min = us.front();
+    return LSB_OK;
 }
 
 }  // extern "C"

@@ -42,7 +42,7 @@ static const any_fn entry_points[] = {
     (any_fn)lsb_time_next_launch, (any_fn)lsb_stream_reference, (any_fn)lsb_serve_simulate,
     (any_fn)lsb_last_error,     (any_fn)lsb_version,         (any_fn)lsb_job_extents,
     (any_fn)lsb_slice_stream_bytes, (any_fn)lsb_embed_verify,  (any_fn)lsb_batch_run_static,
-    (any_fn)lsb_batch_tune_get_op, (any_fn)lsb_batch_tune_set_op,
+    (any_fn)lsb_batch_tune_get_op, (any_fn)lsb_batch_tune_set_op, (any_fn)lsb_roundtrip_latency,
 };
 
 static int check(int cond, const char *what) {
