@@ -281,7 +281,11 @@ int lsb_plan_create(lsb_plan **plan, const lsb_job *jobs_host, int n_jobs, int o
  * work.  Waits for the plan's previous run to have read the job table. */
 int lsb_plan_update(lsb_plan *plan, const lsb_job *jobs_host, int n_jobs);
 
-/* Run every job of the plan on `stream`.  For job j: status_dev[j] <- LSB_OK
+/* Run every job of the plan on `stream`.  Every run of a plan uses the
+ * plan's device job table and tile counter: a run on another stream than
+ * the plan's previous run first makes `stream` wait for that run.  The job
+ * table is uploaded again only after lsb_plan_update.
+ * For job j: status_dev[j] <- LSB_OK
  * or its error; for extract jobs len_dev[j] <- decoded length, 0 for raw
  * slices (len_dev may be NULL if the plan has no extract job).  Results are
  * identical to one lsb_embed / lsb_extract call per job (raw slices:
