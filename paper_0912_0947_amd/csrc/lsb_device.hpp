@@ -120,23 +120,6 @@ __device__ __forceinline__ void store16(uint8_t *p, u32x4 v) {
 
 __device__ __forceinline__ uint32_t bswap32(uint32_t x) { return __builtin_bswap32(x); }
 
-// Stream-side accesses through the global address space.  Stream addresses
-// are computed as integers (base + 2k bytes per vector), which loses the
-// pointer's address space: the compiler then emits flat instructions, which
-// wait on both the vector-memory and the LDS counters and were scheduled
-// with a full wait before the vector's cover load was even issued.  Every
-// buffer of the library is device (global) memory, so the accesses are
-// written as global ones.
-template <typename T>
-__device__ __forceinline__ T gload(const void *p) {
-    return *reinterpret_cast<const __attribute__((address_space(1))) T *>(reinterpret_cast<uintptr_t>(p));
-}
-
-template <typename T>
-__device__ __forceinline__ void gstore(void *p, T v) {
-    *reinterpret_cast<__attribute__((address_space(1))) T *>(reinterpret_cast<uintptr_t>(p)) = v;
-}
-
 // Logical stream byte s (header bytes come from the header value).
 __device__ __forceinline__ uint32_t stream_byte(const Span &s, uint64_t i) {
     if (i < s.hdr_len) return (s.hdr >> (8 * (3 - (uint32_t)i))) & 0xFFu;
@@ -153,12 +136,14 @@ template <int K>
 __device__ __forceinline__ void load_chunk_words(const uint8_t *p, uint32_t *w) {
     if constexpr (K % 2 == 0) {
 #pragma unroll
-        for (int i = 0; i < K / 2; ++i) w[i] = bswap32(gload<uint32_t>(p + 4 * i));
+        for (int i = 0; i < K / 2; ++i)
+            w[i] = bswap32(reinterpret_cast<const uint32_t *>(p)[i]);
     } else {
+        const uint16_t *h = reinterpret_cast<const uint16_t *>(p);
 #pragma unroll
         for (int i = 0; i < K / 2; ++i)
-            w[i] = bswap32((uint32_t)gload<uint16_t>(p + 4 * i) | ((uint32_t)gload<uint16_t>(p + 4 * i + 2) << 16));
-        w[K / 2] = bswap32((uint32_t)gload<uint16_t>(p + 2 * (K - 1)));
+            w[i] = bswap32((uint32_t)h[2 * i] | ((uint32_t)h[2 * i + 1] << 16));
+        w[K / 2] = bswap32((uint32_t)h[K - 1]);
     }
 }
 
@@ -169,8 +154,8 @@ __device__ __forceinline__ void load_chunk_bytes(const uint8_t *p, uint32_t r, u
     constexpr int NB = 2 * K;
     uint32_t b[NB + 1];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) b[i] = gload<uint8_t>(p + i);
-    b[NB] = r ? gload<uint8_t>(p + NB) : 0u;
+    for (int i = 0; i < NB; ++i) b[i] = p[i];
+    b[NB] = r ? p[NB] : 0u;
     uint32_t W[Chunk<K>::NW + 1];
 #pragma unroll
     for (int i = 0; i <= Chunk<K>::NW; ++i) {
@@ -274,15 +259,16 @@ template <int K>
 __device__ __forceinline__ void store_chunk_words(uint8_t *p, const uint32_t *w) {
     if constexpr (K % 2 == 0) {
 #pragma unroll
-        for (int i = 0; i < K / 2; ++i) gstore<uint32_t>(p + 4 * i, bswap32(w[i]));
+        for (int i = 0; i < K / 2; ++i) reinterpret_cast<uint32_t *>(p)[i] = bswap32(w[i]);
     } else {
+        uint16_t *h = reinterpret_cast<uint16_t *>(p);
 #pragma unroll
         for (int i = 0; i < K / 2; ++i) {
             const uint32_t le = bswap32(w[i]);
-            gstore<uint16_t>(p + 4 * i, (uint16_t)le);
-            gstore<uint16_t>(p + 4 * i + 2, (uint16_t)(le >> 16));
+            h[2 * i] = (uint16_t)le;
+            h[2 * i + 1] = (uint16_t)(le >> 16);
         }
-        gstore<uint16_t>(p + 2 * (K - 1), (uint16_t)bswap32(w[K / 2]));
+        h[K - 1] = (uint16_t)bswap32(w[K / 2]);
     }
 }
 
@@ -340,13 +326,10 @@ __device__ __forceinline__ uint32_t extract_stream_byte(const Span &s, uint64_t 
 // vectors [v_begin, v_end) of a span in groups of 64*UNR vectors; wave
 // `wave` takes groups wave, wave + n_waves, ...
 
-// WORDS: the stream side of fast vectors uses dword/short accesses (s.words),
-// fixed per walk so that no branch separates a vector's stream loads from
-// its cover load and the loads of a group issue back to back.
-template <int K, int UNR, bool NT, bool WORDS>
-__device__ __forceinline__ void embed_walk_as(const Span &s, const Ranges &r, uint64_t v_begin,
-                                              uint64_t v_end, uint64_t wave, uint64_t n_waves,
-                                              uint32_t lane) {
+template <int K, int UNR, bool NT>
+__device__ __forceinline__ void embed_walk(const Span &s, const Ranges &r, uint64_t v_begin,
+                                           uint64_t v_end, uint64_t wave, uint64_t n_waves,
+                                           uint32_t lane) {
     constexpr uint64_t G = 64 * UNR;
     const uint64_t sb = stream_byte0(s);
     const uint32_t rbit = (uint32_t)(((uint64_t)K * s.t0) & 7);
@@ -362,7 +345,7 @@ __device__ __forceinline__ void embed_walk_as(const Span &s, const Ranges &r, ui
                 const uint64_t u = u0 + (uint64_t)j * 64 + lane;
                 c[j] = load16<NT>(s.src + 16 * u);
                 const uint8_t *p = reinterpret_cast<const uint8_t *>(body_base + 2 * K * u);
-                if constexpr (WORDS) load_chunk_words<K>(p, w[j]);
+                if (s.words) load_chunk_words<K>(p, w[j]);
                 else load_chunk_bytes<K>(p, rbit, w[j]);
             }
 #pragma unroll
@@ -387,7 +370,7 @@ __device__ __forceinline__ void embed_walk_as(const Span &s, const Ranges &r, ui
                 if (u >= r.fast_begin && u < r.fast_end) {
                     uint32_t w[Chunk<K>::NW];
                     const uint8_t *p = reinterpret_cast<const uint8_t *>(body_base + 2 * K * u);
-                    if constexpr (WORDS) load_chunk_words<K>(p, w);
+                    if (s.words) load_chunk_words<K>(p, w);
                     else load_chunk_bytes<K>(p, rbit, w);
                     store16<NT>(s.dst + 16 * u, embed_vec<K>(load16<NT>(s.src + 16 * u), w));
                 } else if (u >= r.copy_begin && u < r.copy_end) {
@@ -399,14 +382,6 @@ __device__ __forceinline__ void embed_walk_as(const Span &s, const Ranges &r, ui
             }
         }
     }
-}
-
-template <int K, int UNR, bool NT>
-__device__ __forceinline__ void embed_walk(const Span &s, const Ranges &r, uint64_t v_begin,
-                                           uint64_t v_end, uint64_t wave, uint64_t n_waves,
-                                           uint32_t lane) {
-    if (s.words) embed_walk_as<K, UNR, NT, true>(s, r, v_begin, v_end, wave, n_waves, lane);
-    else embed_walk_as<K, UNR, NT, false>(s, r, v_begin, v_end, wave, n_waves, lane);
 }
 
 // Store the stream bytes of one fast wave group whose stego vectors are in c.
@@ -423,7 +398,7 @@ __device__ __forceinline__ void extract_store_group(const Span &s, uintptr_t out
             store_chunk_words<K>(p, w);
         } else {
 #pragma unroll
-            for (int i = 0; i < 2 * K; ++i) gstore<uint8_t>(p + i, (uint8_t)(w[i >> 2] >> (24 - 8 * (i & 3))));
+            for (int i = 0; i < 2 * K; ++i) p[i] = (uint8_t)(w[i >> 2] >> (24 - 8 * (i & 3)));
         }
     }
 }
@@ -453,11 +428,11 @@ __device__ __forceinline__ void extract_store_group_ballot(const Span &s, uintpt
             const uint64_t v = __builtin_bswap64(__builtin_bitreverse64(mine));
             uint8_t *p = reinterpret_cast<uint8_t *>(out_base + 2 * (u0 + (uint64_t)j * 64) + 8 * lane);
             if (s.words) {
-                gstore<uint32_t>(p, (uint32_t)v);
-                gstore<uint32_t>(p + 4, (uint32_t)(v >> 32));
+                reinterpret_cast<uint32_t *>(p)[0] = (uint32_t)v;
+                reinterpret_cast<uint32_t *>(p)[1] = (uint32_t)(v >> 32);
             } else {
 #pragma unroll
-                for (int b = 0; b < 8; ++b) gstore<uint8_t>(p + b, (uint8_t)(v >> (8 * b)));
+                for (int b = 0; b < 8; ++b) p[b] = (uint8_t)(v >> (8 * b));
             }
         }
     }
@@ -498,7 +473,7 @@ __device__ __forceinline__ void extract_walk(const Span &s, const Ranges &r, uin
                     if (s.words) {
                         store_chunk_words<K>(p, w);
                     } else {
-                        for (int i = 0; i < 2 * K; ++i) gstore<uint8_t>(p + i, (uint8_t)(w[i >> 2] >> (24 - 8 * (i & 3))));
+                        for (int i = 0; i < 2 * K; ++i) p[i] = (uint8_t)(w[i >> 2] >> (24 - 8 * (i & 3)));
                     }
                 } else {
                     const uint64_t i0 = sb + 2 * K * u;

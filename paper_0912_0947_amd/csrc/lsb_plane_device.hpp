@@ -279,7 +279,7 @@ __device__ __forceinline__ void plane_extract_vec_out(const Span &s, const u32x4
         store_chunk_words<K>(p, w);
     } else {
 #pragma unroll
-        for (int i = 0; i < 2 * K; ++i) gstore<uint8_t>(p + i, (uint8_t)(w[i >> 2] >> (24 - 8 * (i & 3))));
+        for (int i = 0; i < 2 * K; ++i) p[i] = (uint8_t)(w[i >> 2] >> (24 - 8 * (i & 3)));
     }
 }
 
