@@ -324,9 +324,9 @@ int lsb_extract_batch(lsb_plan *plan, const uint8_t *stego_arena,
 int lsb_job_extents(const lsb_job *jobs, int n_jobs, int op,
                     uint64_t *extents);
 
-/* For callers that cannot allocate (code under HIP graph capture, serving
- * loops that may not call hipMalloc): lsb_plan_create + lsb_plan_run in one
- * call that allocates nothing.  The job table and its tile counter go into a
+/* For callers that cannot allocate (serving loops and harnesses that may not
+ * call hipMalloc): lsb_plan_create + lsb_plan_run in one call that allocates
+ * nothing.  The job table and its tile counter go into a
  * fixed device array of the library (one per device, about 256 KiB, held
  * until the process ends) instead of plan memory; the table is staged in a
  * library host buffer and uploaded with an asynchronous copy on `stream`,
@@ -337,7 +337,9 @@ int lsb_job_extents(const lsb_job *jobs, int n_jobs, int op,
  * call on one device shares that device's table: calls on one stream run in
  * order, but calls on different streams of one device whose work overlaps
  * race and must not be made.  Host threads are serialised while the table is
- * filled and uploaded. */
+ * filled and uploaded.  A stream that is capturing a graph is refused
+ * (LSB_E_ARG, nothing enqueued): the captured upload would read the shared
+ * staging buffer at each replay, after later calls may have refilled it. */
 enum { LSB_STATIC_MAX_JOBS = 4096 };
 int lsb_batch_run_static(const lsb_job *jobs, int n_jobs, int op,
                          const uint8_t *cover_arena, uint8_t *stego_arena,

@@ -588,6 +588,15 @@ int lsb_batch_run_static(const lsb_job *jobs, int n_jobs, int op, const uint8_t 
     if (rc != LSB_OK) return rc;
     const int64_t tv = batch_tile_vectors();
     hipStream_t st = (hipStream_t)stream;
+    // Under stream capture the table upload would become a graph node that
+    // reads the staging buffer below at every replay, after later calls may
+    // have refilled it: such a call is refused before anything is enqueued.
+    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(st, &capture);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    if (capture != hipStreamCaptureStatusNone)
+        return fail(LSB_E_ARG, "lsb_batch_run_static: the stream is capturing a graph (the job table's upload "
+                               "would read a shared staging buffer at each replay)");
     // One host staging table for all devices: filled and uploaded under the
     // lock.  An upload from pageable memory has read the source when
     // hipMemcpyAsync returns, so the next call may refill it.
@@ -601,7 +610,7 @@ int lsb_batch_run_static(const lsb_job *jobs, int n_jobs, int op, const uint8_t 
     if (tv_now != tv) return fail(LSB_E_ARG, "lsb_batch_run_static: tile size changed during the call");
     if (t.has_extract && !len_dev) return fail(LSB_E_ARG, "lsb_batch_run_static: extract jobs need len_dev");
     if (t.has_embed && !cover_arena) return fail(LSB_E_ARG, "lsb_batch_run_static: embed jobs need a cover arena");
-    hipError_t e = hipMemcpyAsync(table, g_static_host, t.used_bytes, hipMemcpyHostToDevice, st);
+    e = hipMemcpyAsync(table, g_static_host, t.used_bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(static job table)");
     const PlanHeader *hdr = (const PlanHeader *)table;
     const DevJob *dj = (const DevJob *)(table + sizeof(PlanHeader));

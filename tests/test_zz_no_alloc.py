@@ -1,7 +1,8 @@
 """lsb_batch_run_static, the allocation-free batched call: its results equal
 those of a plan (lsb_plan_create + lsb_plan_run) on the same jobs, byte for
 byte, on two calls in a row (the second with fewer jobs), and job counts
-beyond its fixed table are refused before anything runs."""
+beyond its fixed table, or a stream that is capturing a graph, are refused
+before anything runs."""
 import numpy as np
 import pytest
 import torch
@@ -89,3 +90,32 @@ def test_static_refuses_more_jobs_than_its_table():
     batch.run_static(jobs[:batch.STATIC_MAX_JOBS], OP_EMBED, cover, stego, msg, None, status)
     torch.cuda.synchronize()
     assert bool((status[:batch.STATIC_MAX_JOBS] == OK).all()) and int(status[-1]) == 99
+
+
+def test_static_refuses_a_capturing_stream():
+    """Under stream capture the table upload would be a graph node reading
+    the library's shared staging buffer at replay time: the call is refused
+    before anything is enqueued, and the same call outside capture runs."""
+    wl = BatchWorkload(8, oracle.capacity, seed=3121, lo=16, hi=64)
+    cover, stego, msg, _ = wl.allocate(DEV)
+    jobs = wl.jobs(OP_EMBED)
+    status = torch.full((jobs.size,), 99, dtype=torch.int32, device=DEV)
+    mark = torch.zeros(1, dtype=torch.int32, device=DEV)
+    side = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        graph.capture_begin()
+        try:
+            mark.add_(1)  # the captured graph is not empty
+            with pytest.raises(LsbError) as e:
+                batch.run_static(jobs, OP_EMBED, cover, stego, msg, None, status, stream=side)
+        finally:
+            graph.capture_end()
+    assert e.value.code == E_ARG and "capturing" in str(e.value)
+    del graph
+    torch.cuda.synchronize()
+    assert bool((status == 99).all()) and int(mark) == 0, "nothing ran during the capture"
+    batch.run_static(jobs, OP_EMBED, cover, stego, msg, None, status)
+    torch.cuda.synchronize()
+    assert bool((status == OK).all())
