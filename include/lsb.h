@@ -400,9 +400,12 @@ int lsb_batch_tune_set_op(int op, const lsb_launch_cfg *cfg);
  * Serving loop: an open-loop stream of embed and extract requests served
  * with continuous batching.  Requests are admitted in arrival order when the
  * HBM budget (the caller's arena) has room for their outputs; admitted
- * requests are packed into the next batched launch on any free slot (one
- * plan + stream each), so batches overlap on the device and requests that
- * arrive while others run join the next launch.  Stego buffers stay device
+ * requests are packed into the next launch on any free slot (one stream
+ * each), so launches overlap on the device and requests that arrive while
+ * others run join the next launch.  A launch of up to four jobs of one
+ * operation runs them through lsb_embed / lsb_extract (one kernel each);
+ * more go through the slot's batched plan for that operation.  Either way
+ * each job's result and status are the same.  Stego buffers stay device
  * resident until an extract consumes them (then they are freed) or the budget
  * needs their space (oldest first, counted as evictions).
  */

@@ -141,7 +141,10 @@ class HipExecutor : public Executor {
             if (s.len_host) (void)hipHostFree(s.len_host);
         }
     }
-    // status_off / len_off: arena offsets of 2*B int32 / uint32 per slot
+    // status_off / len_off: arena offsets of 2*B int32 / uint32 per slot.
+    // Embed jobs report their status in status_dev[0, B); extract jobs their
+    // decoded length in len_dev[0, B) and their status right after it, in
+    // len_dev[B, 2B), so one copy brings an extract launch's results back.
     int init(const std::vector<uint64_t> &status_off, const std::vector<uint64_t> &len_off) {
         for (size_t i = 0; i < s_.size(); ++i) {
             S &s = s_[i];
@@ -165,18 +168,25 @@ class HipExecutor : public Executor {
         const int cnt[2] = {ne, nx};
         for (int op = 0; op < 2; ++op) {
             if (!cnt[op]) continue;
+            if (cnt[op] <= kDirectMax) {
+                const int rc = launch_direct(s, op, jobs[op], cnt[op]);
+                if (rc != LSB_OK) return rc;
+                continue;
+            }
             int rc = lsb_plan_update(s.plan[op], jobs[op], cnt[op]);
             if (rc != LSB_OK) return rc;
-            int32_t *st = s.status_dev + op * B_;
-            uint32_t *ln = s.len_dev + op * B_;
-            rc = lsb_plan_run(s.plan[op], op == LSB_OP_EMBED ? cfg_->cover_pool : nullptr, cfg_->arena,
-                              op == LSB_OP_EMBED ? (uint8_t *)cfg_->msg_pool : cfg_->arena, ln, st, s.stream);
+            const bool emb = op == LSB_OP_EMBED;
+            int32_t *st = emb ? s.status_dev : (int32_t *)(s.len_dev + B_);
+            uint32_t *ln = emb ? nullptr : s.len_dev;
+            rc = lsb_plan_run(s.plan[op], emb ? cfg_->cover_pool : nullptr, cfg_->arena,
+                              emb ? (uint8_t *)cfg_->msg_pool : cfg_->arena, ln, st, s.stream);
             if (rc != LSB_OK) return rc;
-            hipError_t e = hipMemcpyAsync(s.status_host + op * B_, st, sizeof(int32_t) * cnt[op],
-                                          hipMemcpyDeviceToHost, s.stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(s.len_host + op * B_, ln, sizeof(uint32_t) * cnt[op], hipMemcpyDeviceToHost,
-                                   s.stream);
+            // one copy per launch: embed statuses, or an extract's lengths
+            // together with the statuses that follow them
+            const hipError_t e =
+                emb ? hipMemcpyAsync(s.status_host, st, sizeof(int32_t) * cnt[op], hipMemcpyDeviceToHost, s.stream)
+                    : hipMemcpyAsync(s.len_host, ln, sizeof(uint32_t) * ((size_t)B_ + cnt[op]), hipMemcpyDeviceToHost,
+                                     s.stream);
             if (e != hipSuccess) return hip_fail(e, "lsb_serve: status copy");
         }
         const hipError_t e = hipEventRecord(s.done, s.stream);
@@ -196,14 +206,52 @@ class HipExecutor : public Executor {
         *done = true;
         return LSB_OK;
     }
-    int32_t status(int slot, int op, int j) const override { return s_[slot].status_host[op * B_ + j]; }
-    uint32_t length(int slot, int op, int j) const override { return s_[slot].len_host[op * B_ + j]; }
+    int32_t status(int slot, int op, int j) const override {
+        const S &s = s_[slot];
+        return op == LSB_OP_EMBED ? s.status_host[j] : (int32_t)s.len_host[B_ + j];
+    }
+    uint32_t length(int slot, int op, int j) const override {
+        return op == LSB_OP_EXTRACT ? s_[slot].len_host[j] : 0u;
+    }
     double now() override {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
     }
     void idle(double) override {}
 
    private:
+    struct S;
+    // A launch of at most kDirectMax jobs issues them through the plain entry
+    // points, one kernel each, instead of a plan (no table upload, prologue
+    // or graph): a plan's host-side cost is that of about five plain
+    // launches.  Results and statuses are those a plan reports.  An embed
+    // over capacity is refused on the host and its status set here; extracts
+    // report decoded lengths and statuses on the device, in the same places
+    // as a plan's, and one copy brings them back.
+    static constexpr int kDirectMax = 4;
+    int launch_direct(S &s, int op, const lsb_job *jobs, int cnt) {
+        if (op == LSB_OP_EMBED) {
+            for (int j = 0; j < cnt; ++j) {
+                const lsb_job &J = jobs[j];
+                const int rc = lsb_embed(cfg_->cover_pool + J.cover_off, cfg_->arena + J.stego_off, J.n,
+                                         cfg_->msg_pool + J.msg_off, J.len, J.k, s.stream);
+                if (rc != LSB_OK && rc != LSB_E_CAPACITY) return rc;
+                clear_error();  // a refused job is a status, not an error of the run
+                s.status_host[j] = rc;
+            }
+            return LSB_OK;
+        }
+        uint32_t *ln = s.len_dev;
+        int32_t *st = (int32_t *)(s.len_dev + B_);
+        for (int j = 0; j < cnt; ++j) {
+            const lsb_job &J = jobs[j];
+            const int rc = lsb_extract(cfg_->arena + J.stego_off, J.n, J.k, cfg_->arena + J.msg_off, J.msg_cap, ln + j,
+                                       st + j, s.stream);
+            if (rc != LSB_OK) return rc;
+        }
+        const hipError_t e = hipMemcpyAsync(s.len_host, ln, sizeof(uint32_t) * ((size_t)B_ + cnt),
+                                            hipMemcpyDeviceToHost, s.stream);
+        return e == hipSuccess ? LSB_OK : hip_fail(e, "lsb_serve: status copy");
+    }
     struct S {
         lsb_plan *plan[2] = {nullptr, nullptr};
         hipStream_t stream = nullptr;

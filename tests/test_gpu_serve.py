@@ -83,6 +83,30 @@ def test_mix_equals_alone(pool, rate, slots, max_batch):
     assert np.all(res["admit_s"] + 1e-9 >= req["arrival_s"])
 
 
+@pytest.mark.parametrize("bursts", [True, False])
+def test_direct_and_plan_launches(pool, bursts):
+    """Launches of at most four jobs go through the plain entry points, more
+    through a batched plan; both report the plan's results and statuses.  Two
+    bursts (half the requests at once, the other half 20 ms later, when the
+    first half's stego buffers are resident for its extracts; one slot) fill
+    launches far past four jobs, so most requests run in plans; arrivals 2 ms
+    apart run one request per launch.  Every request is checked against the
+    oracle."""
+    wl, cover, msg = pool
+    n, max_batch = 240, 64
+    req, ids = serve.poisson_requests(wl, 1000.0, n, seed=641)
+    req["arrival_s"] = np.where(np.arange(n) < n // 2, 0.0, 0.02) if bursts else np.arange(n) * 2e-3
+    arena = torch.empty(int(wl.n.sum()) * 4 + (64 << 20), dtype=torch.uint8, device=DEV)
+    res, stats = serve.serve(arena, cover, msg, req, max_batch=max_batch, n_slots=1, keep_outputs=True)
+    assert stats["rejected"] == 0 and stats["evictions"] == 0
+    if bursts:
+        assert stats["launches"] < n // 4, "launches of at most four jobs each would need %d" % (n // 4)
+    else:
+        assert stats["launches"] >= n * 9 // 10
+    n_extract = _check_results(wl, cover, msg, arena, req, res, ids)
+    assert n_extract > 20
+
+
 def test_budget_bounds_memory_and_evicts(pool):
     """A budget of a few covers: admission waits for memory, resident stego
     buffers are evicted oldest first, the high-water mark never exceeds the
