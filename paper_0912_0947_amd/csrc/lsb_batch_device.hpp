@@ -138,12 +138,12 @@ __device__ __forceinline__ void run_tile(const DevJob &J, uint64_t v_begin, uint
 
 // Waves per SIMD the launch bound asks for.  A 1024-thread block puts 4
 // waves on each SIMD (so at most 128 VGPRs), and anything from 4 to 7 keeps
-// one block per CU; only 8 fits two.  8 at one vector per lane (about 40
-// VGPRs) and 6 at two (75 with all sixteen walkers behind one switch); the
-// extract-any-k class asks for 8 at two (its 61 VGPRs fit the 64 that two
-// blocks per CU leave); the raw-capable kernels with the widest walkers (the
-// switch, or k = 1 embed) take 5 (96 VGPRs) at two vectors per lane, where 6
-// would spill.
+// one block per CU; only 8 (64 VGPRs) fits two.  8 at one vector per lane
+// (about 30-40 VGPRs) and for the extract-any-k class at two (43 VGPRs, 57
+// with raw slices); 6 for the others at two, 5 for the raw-capable kernels
+// with the widest walkers (all sixteen behind the switch: 85 VGPRs; k = 1
+// embed), where 6 would spill; 4 at four (the extract-any-k class then uses
+// 85 VGPRs, one block per CU).
 template <int UNR, int CLS, bool RAW>
 constexpr int batch_min_waves() {
     if constexpr (UNR == 1) return 8;
