@@ -385,21 +385,26 @@ __device__ __forceinline__ void embed_walk(const Span &s, const Ranges &r, uint6
 }
 
 // Store the stream bytes of one fast wave group whose stego vectors are in c.
+// Every vector of the group is extracted before the first store, and the
+// stores sit in one branch on the stream side's width: with a branch per
+// vector, the wait inserted where the two store paths join made the wave
+// wait for each vector's store to complete before extracting the next.
 template <int K, int UNR>
 __device__ __forceinline__ void extract_store_group(const Span &s, uintptr_t out_base, uint64_t u0,
                                                     const u32x4 *c, uint32_t lane) {
+    uint32_t w[UNR][Chunk<K>::NW];
 #pragma unroll
-    for (int j = 0; j < UNR; ++j) {
-        const uint64_t u = u0 + (uint64_t)j * 64 + lane;
-        uint32_t w[Chunk<K>::NW];
-        extract_vec<K>(c[j], w);
-        uint8_t *p = reinterpret_cast<uint8_t *>(out_base + 2 * K * u);
-        if (s.words) {
-            store_chunk_words<K>(p, w);
-        } else {
+    for (int j = 0; j < UNR; ++j) extract_vec<K>(c[j], w[j]);
+    uint8_t *p0 = reinterpret_cast<uint8_t *>(out_base + 2 * K * (u0 + lane));
+    if (s.words) {
 #pragma unroll
-            for (int i = 0; i < 2 * K; ++i) p[i] = (uint8_t)(w[i >> 2] >> (24 - 8 * (i & 3)));
-        }
+        for (int j = 0; j < UNR; ++j) store_chunk_words<K>(p0 + 2 * K * 64 * j, w[j]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < UNR; ++j)
+#pragma unroll
+            for (int i = 0; i < 2 * K; ++i)
+                p0[2 * K * 64 * j + i] = (uint8_t)(w[j][i >> 2] >> (24 - 8 * (i & 3)));
     }
 }
 
