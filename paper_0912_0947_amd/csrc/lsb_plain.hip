@@ -27,12 +27,32 @@ namespace lsb {
 // ---------------------------------------------------------------------------
 // Kernels.
 
+// Block order of the embed and extract kernels.  Workgroups go to the eight
+// XCDs in turn, so neighbouring blocks sit on different XCDs (each with its
+// own L2), and a line that two neighbours share is moved by both: the embed's
+// stream bytes straddle a line at each end of a block (the 4-byte header sits
+// in front of the message), and an extract block's 2k-byte outputs end
+// inside a line.  Logical blocks are therefore handed out in runs of 16 per
+// XCD (physical block b on XCD b % 8 takes logical block
+// 128 (s / 16) + 16 x + s % 16, s = b / 8): the neighbours inside a run share
+// an L2, and the XCDs still interleave at 16-block granularity (handing each
+// XCD one contiguous eighth removed the shared lines too, but made every
+// XCD stream its own distant region and slowed the grid-stride launches).
+// Blocks past the last whole round of 128 keep their index.
+__device__ __forceinline__ uint32_t xcd_run_block(uint32_t b, uint32_t grid) {
+    constexpr uint32_t kXcds = 8, kRun = 16, kRound = kXcds * kRun;
+    if (b >= grid / kRound * kRound) return b;
+    const uint32_t x = b % kXcds, slot = b / kXcds;
+    return (slot / kRun) * kRound + x * kRun + slot % kRun;
+}
+
 // Vector embed over the whole span; grid-stride over wave groups.
 template <int K, int UNR, bool NT>
 __global__ void __launch_bounds__(1024) lsb_embed_kernel(Span s) {
     const Ranges r = embed_ranges<K>(s);
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t block = xcd_run_block(blockIdx.x, gridDim.x);
+    const uint64_t wave = (block * blockDim.x + threadIdx.x) >> 6;
     const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     embed_walk<K, UNR, NT>(s, r, 0, r.count, wave, n_waves, lane);
 }
@@ -53,7 +73,8 @@ __global__ void __launch_bounds__(1024)
     __shared__ __attribute__((aligned(16))) uint8_t stage_all[BALLOT ? 16 * 1024 : 16];
     uint8_t *stage = BALLOT ? stage_all + 1024 * (threadIdx.x >> 6) : nullptr;
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t block = xcd_run_block(blockIdx.x, gridDim.x);
+    const uint64_t wave = (block * blockDim.x + threadIdx.x) >> 6;
     const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     if (!header) {
         const Ranges r = extract_ranges<K>(s);
