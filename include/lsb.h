@@ -365,6 +365,10 @@ typedef struct lsb_launch_cfg {
     int32_t nontemporal;    /* 1 = streaming (non-temporal) loads/stores   */
     int32_t pack;           /* extract, k = 1: 0 = per-lane multiply pack,
                                1 = wavefront ballots staged through LDS    */
+    int32_t order;          /* block order on the 8 XCDs, which take blocks
+                               in turn: 0 = launch order, 1 = runs of 16
+                               consecutive blocks per XCD (neighbouring
+                               blocks then share an L2); embed and extract */
 } lsb_launch_cfg;
 
 int lsb_tune_get(int op, int k, uint64_t n, lsb_launch_cfg *cfg);

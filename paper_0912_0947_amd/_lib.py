@@ -37,7 +37,7 @@ ERROR_NAMES = {
 class LaunchCfg(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("unroll", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
-                ("pack", ctypes.c_int32)]
+                ("pack", ctypes.c_int32), ("order", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

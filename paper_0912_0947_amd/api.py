@@ -298,8 +298,8 @@ def tune_get(op: int, k: int, n: int) -> dict:
 
 
 def tune_set(op: int, k: int, bucket: int, block: int, unroll: int, blocks_per_cu: int, nontemporal: int,
-             pack: int = 0):
-    cfg = LaunchCfg(block, unroll, blocks_per_cu, nontemporal, pack)
+             pack: int = 0, order: int = 0):
+    cfg = LaunchCfg(block, unroll, blocks_per_cu, nontemporal, pack, order)
     check(lib().lsb_tune_set(op, k, bucket, ctypes.byref(cfg)))
 
 

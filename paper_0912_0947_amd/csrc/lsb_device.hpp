@@ -49,6 +49,7 @@ struct Span {
     int k;
     int inplace;          // embed: dst == src, skip copy-only bytes
     int words;            // stream side may use dword/short accesses
+    int block_order;      // plain kernels: 1 = blocks in runs of 16 per XCD
 };
 
 // Vector classes of a span (all in the span's own vector index space).

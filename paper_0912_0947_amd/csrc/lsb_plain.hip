@@ -27,9 +27,10 @@ namespace lsb {
 // ---------------------------------------------------------------------------
 // Kernels.
 
-// Block order of the embed and extract kernels.  Workgroups go to the eight
-// XCDs in turn, so neighbouring blocks sit on different XCDs (each with its
-// own L2), and a line that two neighbours share is moved by both: the embed's
+// Block order of the embed and extract kernels (launch configuration field
+// `order`; Span.block_order).  Workgroups go to the eight XCDs in turn, so
+// neighbouring blocks sit on different XCDs (each with its own L2), and a
+// line that two neighbours share is moved by both: the embed's
 // stream bytes straddle a line at each end of a block (the 4-byte header sits
 // in front of the message), and an extract block's 2k-byte outputs end
 // inside a line.  Logical blocks are therefore handed out in runs of 16 per
@@ -51,7 +52,7 @@ template <int K, int UNR, bool NT>
 __global__ void __launch_bounds__(1024) lsb_embed_kernel(Span s) {
     const Ranges r = embed_ranges<K>(s);
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t block = xcd_run_block(blockIdx.x, gridDim.x);
+    const uint64_t block = s.block_order ? xcd_run_block(blockIdx.x, gridDim.x) : blockIdx.x;
     const uint64_t wave = (block * blockDim.x + threadIdx.x) >> 6;
     const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     embed_walk<K, UNR, NT>(s, r, 0, r.count, wave, n_waves, lane);
@@ -73,7 +74,7 @@ __global__ void __launch_bounds__(1024)
     __shared__ __attribute__((aligned(16))) uint8_t stage_all[BALLOT ? 16 * 1024 : 16];
     uint8_t *stage = BALLOT ? stage_all + 1024 * (threadIdx.x >> 6) : nullptr;
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t block = xcd_run_block(blockIdx.x, gridDim.x);
+    const uint64_t block = s.block_order ? xcd_run_block(blockIdx.x, gridDim.x) : blockIdx.x;
     const uint64_t wave = (block * blockDim.x + threadIdx.x) >> 6;
     const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     if (!header) {
@@ -234,6 +235,7 @@ static int stream_words(const void *base, uint32_t hdr_len, const Span &s) {
 int launch_embed(const Span &s0, const lsb_launch_cfg &c, hipStream_t stream) {
     Span s = s0;
     s.words = stream_words(s.body, s.hdr_len, s);
+    s.block_order = c.order;
     if (!aligned16(s.src) || !aligned16(s.dst)) {
         // per-byte kernel over the bytes that must be written
         uint64_t count = s.n;
@@ -264,6 +266,7 @@ int launch_extract(const Span &s0, int header, uint64_t out_cap, uint32_t *len_o
                    uint64_t max_vectors, const lsb_launch_cfg &c, hipStream_t stream) {
     Span s = s0;
     s.words = stream_words(s.out, s.hdr_len, s);
+    s.block_order = c.order;
     if (!aligned16(s.src)) {
         uint64_t bytes = max_vectors * 2 * (uint64_t)s.k;  // output stream bytes bound
         uint64_t blocks = ceil_div(bytes ? bytes : 1, 256);

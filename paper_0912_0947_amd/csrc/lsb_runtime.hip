@@ -68,14 +68,15 @@ static void tune_defaults() {
     // wave (no grid cap), cached loads/stores.  Replaced by tuned entries.
     for (int op = 0; op < 2; ++op)
         for (int k = 0; k <= 8; ++k)
-            for (int b = 0; b < kBuckets; ++b) g_tune[op][k][b] = lsb_launch_cfg{256, 2, 0, 0, 0};
+            for (int b = 0; b < kBuckets; ++b) g_tune[op][k][b] = lsb_launch_cfg{256, 2, 0, 0, 0, 0};
     g_tune_init = true;
 }
 
 bool cfg_valid(const lsb_launch_cfg &c) {
     return c.block >= 64 && c.block <= 1024 && c.block % 64 == 0 &&
            (c.unroll == 1 || c.unroll == 2 || c.unroll == 4) && c.blocks_per_cu >= 0 &&
-           c.blocks_per_cu <= 64 && (c.nontemporal == 0 || c.nontemporal == 1) && (c.pack == 0 || c.pack == 1);
+           c.blocks_per_cu <= 64 && (c.nontemporal == 0 || c.nontemporal == 1) && (c.pack == 0 || c.pack == 1) &&
+           (c.order == 0 || c.order == 1);
 }
 
 static int bucket_of(uint64_t n) {

@@ -87,13 +87,14 @@ extern "C" int lsb_autotune(int op, int k, uint64_t n, uint8_t *cover, uint8_t *
     double best_t = 1e30;
     lsb_launch_cfg best_c = tune_lookup(op, k, n);
     const int packs = (op == LSB_OP_EXTRACT && k == 1) ? 2 : 1;  // ballot packing exists for k = 1
+    for (int ord = 0; ord < 2 && rc == LSB_OK; ++ord)
     for (int pk = 0; pk < packs && rc == LSB_OK; ++pk)
     for (int nt = 0; nt < 2 && rc == LSB_OK; ++nt)
         for (int b : blocks)
             for (int u : unrolls)
                 for (int c : caps) {
                     if (rc != LSB_OK) break;
-                    const lsb_launch_cfg cfg{b, u, c, nt, pk};
+                    const lsb_launch_cfg cfg{b, u, c, nt, pk, ord};
                     double total = 0;
                     for (int r = 0; r < reps && rc == LSB_OK; ++r) {
                         rc = flush.run(stream);

@@ -24,7 +24,7 @@ KS = range(1, 9)
 # lsb_autotune after a cache flush.
 ROTATE_MIN = 1 << 26
 ROT_SETS = 3
-BLOCKS, UNROLLS, CAPS = (256, 512, 1024), (1, 2, 4), (0, 1, 2, 4, 8, 16)
+BLOCKS, UNROLLS, CAPS, ORDERS = (256, 512, 1024), (1, 2, 4), (0, 1, 2, 4, 8, 16), (0, 1)
 
 
 def bucket(n: int) -> int:
@@ -54,7 +54,8 @@ def load(handle=None, path: str = TABLE) -> bool:
         keys = sorted(tuned)
         for b in range(64):
             c = tuned[min(keys, key=lambda t: (abs(t - b), t))]
-            cfg = LaunchCfg(c["block"], c["unroll"], c["blocks_per_cu"], c["nontemporal"], c.get("pack", 0))
+            cfg = LaunchCfg(c["block"], c["unroll"], c["blocks_per_cu"], c["nontemporal"], c.get("pack", 0),
+                            c.get("order", 0))
             if handle.lsb_tune_set(op, k, b, ctypes.byref(cfg)) != 0:
                 raise RuntimeError("bad tuning entry %s" % c)
     if "batch" in table:
@@ -95,8 +96,8 @@ def tune_rotating(op: int, k: int, n: int, sets, reps: int = 9):
     L = lib()
     cap = api.capacity(n, k)
     packs = (0, 1) if (op == api.OP_EXTRACT and k == 1) else (0,)
-    cands = [{"block": b, "unroll": u, "blocks_per_cu": c, "nontemporal": 1, "pack": pk}
-             for pk in packs for b in BLOCKS for u in UNROLLS for c in CAPS]
+    cands = [{"block": b, "unroll": u, "blocks_per_cu": c, "nontemporal": 1, "pack": pk, "order": o}
+             for o in ORDERS for pk in packs for b in BLOCKS for u in UNROLLS for c in CAPS]
     times = [[] for _ in cands]
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cands]
     for e0, e1 in ev:  # create the HIP events (torch records lazily); the library re-records them
@@ -106,7 +107,8 @@ def tune_rotating(op: int, k: int, n: int, sets, reps: int = 9):
     it = 0
     for r in range(reps + 1):
         for ci, c in enumerate(cands):
-            api.tune_set(op, k, bucket(n), c["block"], c["unroll"], c["blocks_per_cu"], c["nontemporal"], c["pack"])
+            api.tune_set(op, k, bucket(n), c["block"], c["unroll"], c["blocks_per_cu"], c["nontemporal"], c["pack"],
+                         c["order"])
             cover, stego, msg, out, ls = sets[it % len(sets)]
             it += 1
             e0, e1 = ev[ci]
@@ -121,7 +123,7 @@ def tune_rotating(op: int, k: int, n: int, sets, reps: int = 9):
     med = sorted((statistics.median(t) * 1e3, ci) for ci, t in enumerate(times))
     best = cands[med[0][1]]
     api.tune_set(op, k, bucket(n), best["block"], best["unroll"], best["blocks_per_cu"], best["nontemporal"],
-                 best["pack"])
+                 best["pack"], best["order"])
     return best, med[0][0], [(cands[ci], round(us, 2)) for us, ci in med[1:4]]
 
 
@@ -185,22 +187,23 @@ def tune_sequence(n: int = SEQUENCE_N, seq=SEQUENCE, reps: int = 7, log=print):
     torch.cuda.synchronize()
     for op, k in seq:
         best = None
-        for block in BLOCKS:
-            for unroll in UNROLLS:
-                for capb in CAPS:
-                    api.tune_set(op, k, bucket(n), block, unroll, capb, 1, 0)
-                    ms = []
-                    for r in range(reps + 1):
-                        run_sequence((op, k), ev)
-                        torch.cuda.synchronize()
-                        if r:
-                            ms.append(ev[0].elapsed_time(ev[1]))
-                    us = statistics.median(ms) * 1e3
-                    if best is None or us < best[1]:
-                        best = ({"block": block, "unroll": unroll, "blocks_per_cu": capb, "nontemporal": 1,
-                                 "pack": 0}, us)
+        for order in ORDERS:
+            for block in BLOCKS:
+                for unroll in UNROLLS:
+                    for capb in CAPS:
+                        api.tune_set(op, k, bucket(n), block, unroll, capb, 1, 0, order)
+                        ms = []
+                        for r in range(reps + 1):
+                            run_sequence((op, k), ev)
+                            torch.cuda.synchronize()
+                            if r:
+                                ms.append(ev[0].elapsed_time(ev[1]))
+                        us = statistics.median(ms) * 1e3
+                        if best is None or us < best[1]:
+                            best = ({"block": block, "unroll": unroll, "blocks_per_cu": capb, "nontemporal": 1,
+                                     "pack": 0, "order": order}, us)
         c = best[0]
-        api.tune_set(op, k, bucket(n), c["block"], c["unroll"], c["blocks_per_cu"], 1, 0)
+        api.tune_set(op, k, bucket(n), c["block"], c["unroll"], c["blocks_per_cu"], 1, 0, c["order"])
         entries.append({"op": op, "k": k, "bucket": bucket(n), "n": n, "cfg": c, "us": round(best[1], 2),
                         "method": "sequence"})
         log("op=%d k=%d n=%d -> %s %.1f us (in the embed/extract sequence)" % (op, k, n, c, best[1]))

@@ -20,7 +20,7 @@ STATIC_ASSERT(offsetof(lsb_job, msg_cap) == 32 && offsetof(lsb_job, t0) == 40 &&
                   offsetof(lsb_job, stream_bits) == 48 && offsetof(lsb_job, len) == 56 &&
                   offsetof(lsb_job, flags) == 62,
               "lsb_job field offsets");
-STATIC_ASSERT(sizeof(lsb_launch_cfg) == 20, "lsb_launch_cfg is five int32");
+STATIC_ASSERT(sizeof(lsb_launch_cfg) == 24, "lsb_launch_cfg is six int32");
 STATIC_ASSERT(sizeof(lsb_server_cfg) == 48, "lsb_server_cfg is 48 bytes");
 STATIC_ASSERT(sizeof(lsb_request) == 48, "lsb_request is 48 bytes");
 STATIC_ASSERT(sizeof(lsb_result) == 56, "lsb_result is 56 bytes");
@@ -124,6 +124,9 @@ int main(void) {
         bad += check(lsb_batch_tune_get(&c, &tv) == LSB_OK && tv >= 64, "batch tune_get");
         c.block = 100;
         bad += check(lsb_tune_set(LSB_OP_EMBED, 3, 20, &c) == LSB_E_ARG, "invalid block refused");
+        c.block = 256;
+        c.order = 2;
+        bad += check(lsb_tune_set(LSB_OP_EMBED, 3, 20, &c) == LSB_E_ARG, "invalid block order refused");
     }
 
     /* the serving scheduler on its modelled clock: four embeds, then two

@@ -62,7 +62,7 @@ def test_threads_on_their_own_streams():
                             for op in (OP_EMBED, OP_EXTRACT):
                                 cfg = api.tune_get(op, k, cover.size)
                                 api.tune_set(op, k, 20, cfg["block"], cfg["unroll"], cfg["blocks_per_cu"],
-                                             cfg["nontemporal"], cfg["pack"])
+                                             cfg["nontemporal"], cfg["pack"], cfg["order"])
         except BaseException as e:  # reported by the main thread
             failures.append((t, repr(e)))
             try:

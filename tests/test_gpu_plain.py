@@ -426,18 +426,20 @@ def test_every_launch_shape(k):
     out = empty_dev(cap)
     packs = (0, 1) if k == 1 else (0,)
     try:
-        for block in tune.BLOCKS:
-            for unroll in tune.UNROLLS:
-                for capb in tune.CAPS:
-                    for nt in (0, 1):
-                        api.tune_set(api.OP_EMBED, k, -1, block, unroll, capb, nt)
-                        got = api.embed(cd, md, k)
-                        assert torch.equal(got, st), "embed k=%d shape %s" % (k, (block, unroll, capb, nt))
-                        for pack in packs:
-                            api.tune_set(api.OP_EXTRACT, k, -1, block, unroll, capb, nt, pack=pack)
-                            out.fill_(0)
-                            o, ls = api.extract(st, k, out=out)
-                            assert ls.cpu().tolist() == [ln, OK]
-                            assert torch.equal(o[:ln], md), "extract k=%d shape %s" % (k, (block, unroll, capb, nt, pack))
+        for order in tune.ORDERS:
+            for block in tune.BLOCKS:
+                for unroll in tune.UNROLLS:
+                    for capb in tune.CAPS:
+                        for nt in (0, 1):
+                            shape = (block, unroll, capb, nt, order)
+                            api.tune_set(api.OP_EMBED, k, -1, block, unroll, capb, nt, order=order)
+                            got = api.embed(cd, md, k)
+                            assert torch.equal(got, st), "embed k=%d shape %s" % (k, shape)
+                            for pack in packs:
+                                api.tune_set(api.OP_EXTRACT, k, -1, block, unroll, capb, nt, pack=pack, order=order)
+                                out.fill_(0)
+                                o, ls = api.extract(st, k, out=out)
+                                assert ls.cpu().tolist() == [ln, OK]
+                                assert torch.equal(o[:ln], md), "extract k=%d shape %s pack %d" % (k, shape, pack)
     finally:
         tune.load()

@@ -29,7 +29,7 @@ def test_autotune_installs_a_valid_shape(op, k):
         assert us > 0
         assert cfg["block"] in (256, 512, 1024) and cfg["unroll"] in (1, 2, 4)
         assert cfg["blocks_per_cu"] in (0, 1, 2, 4, 8, 16) and cfg["nontemporal"] in (0, 1)
-        assert cfg["pack"] in ((0, 1) if (op == OP_EXTRACT and k == 1) else (0,))
+        assert cfg["pack"] in ((0, 1) if (op == OP_EXTRACT and k == 1) else (0,)) and cfg["order"] in (0, 1)
         assert api.tune_get(op, k, n) == cfg, "the fastest shape is installed for the bucket"
         # launches now use the tuned shape: bit-exact against the oracle
         cover_np = inputs.random_bytes(n, 2701, op, k)
