@@ -726,11 +726,13 @@ def bench_video(api, lib_handle, dev, log_fn, frames=600, h=1080, w=1920):
     return res
 
 
-def bench_serving(api, serve, dev, pool, log_fn, rates=(2000.0, 10000.0, 50000.0), requests=200000,
+def bench_serving(api, serve, dev, pool, log_fn, rates=(2000.0, 10000.0, 50000.0, 200000.0), requests=200000,
                   budget=64 << 30):
     """Open-loop Poisson request streams over the device-resident 4096-cover
     pool, `requests` requests per rate (200,000: 100 s at 2k req/s, 20 s at
-    10k, 4 s at 50k), 50/50 embed/extract, admission by a 64 GB HBM budget.
+    10k, 4 s at 50k, 1 s at 200k, where arrivals outrun one launch per request
+    and launches carry several jobs), 50/50 embed/extract, admission by a
+    64 GB HBM budget.
     Two labelled runs press the budget: one where embeds outnumber extracts
     (30 % extracts), so resident stego buffers pile up past the budget and
     the oldest are evicted; one whose budget (192 MiB) is below what the
