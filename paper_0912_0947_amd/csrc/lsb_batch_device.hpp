@@ -139,15 +139,16 @@ __device__ __forceinline__ void run_tile(const DevJob &J, uint64_t v_begin, uint
 // Waves per SIMD the launch bound asks for.  A 1024-thread block puts 4
 // waves on each SIMD (so at most 128 VGPRs), and anything from 4 to 7 keeps
 // one block per CU; only 8 (64 VGPRs) fits two.  8 at one vector per lane
-// (about 30-40 VGPRs) and for the extract-any-k class at two (43 VGPRs, 57
-// with raw slices); 6 for the others at two, 5 for the raw-capable kernels
-// with the widest walkers (all sixteen behind the switch: 85 VGPRs; k = 1
-// embed), where 6 would spill; 4 at four (the extract-any-k class then uses
-// 85 VGPRs, one block per CU).
+// (about 30-40 VGPRs) and for the extract-any-k class at two (47 VGPRs; with
+// raw slices it would spill under 64 and takes 6); 6 for the others at two,
+// 5 for the raw-capable kernels with the widest walkers (all sixteen behind
+// the switch: 85 VGPRs; k = 1 embed), where 6 would spill; 4 at four (the
+// extract-any-k class then uses 88 VGPRs, 97 with raw slices: one block per
+// CU).
 template <int UNR, int CLS, bool RAW>
 constexpr int batch_min_waves() {
     if constexpr (UNR == 1) return 8;
-    else if constexpr (UNR == 2) return CLS == kClsExtractAnyK ? 8 : (RAW && CLS <= 1 ? 5 : 6);
+    else if constexpr (UNR == 2) return CLS == kClsExtractAnyK && !RAW ? 8 : (RAW && CLS <= 1 ? 5 : 6);
     else return 4;
 }
 
