@@ -263,8 +263,9 @@ typedef struct lsb_plan lsb_plan;
 
 /* Create a plan for n_jobs jobs (1 <= n_jobs <= 2^24).  Allocates device and
  * pinned host memory (this is the only allocating call of the batched form).
- * The plan owns a HIP graph {job-table upload, prologue kernel, persistent
- * kernel} captured on the first run and reused afterwards.
+ * The plan owns a HIP graph {job-table upload, persistent kernel} built on
+ * the first run and reused afterwards (the upload only runs while the table
+ * has changed since the last one).
  *   jobs_host  host array of n_jobs jobs, or NULL to reserve room for n_jobs
  *              jobs and set them later with lsb_plan_update.
  *   op         LSB_OP_EMBED or LSB_OP_EXTRACT: every job of the plan is of
@@ -330,8 +331,7 @@ int lsb_job_extents(const lsb_job *jobs, int n_jobs, int op,
  * fixed device array of the library (one per device, about 256 KiB, held
  * until the process ends) instead of plan memory; the table is staged in a
  * library host buffer and uploaded with an asynchronous copy on `stream`,
- * then the prologue and persistent kernels are launched on `stream` (no
- * graph).  Jobs, arenas, len_dev and status_dev mean what they mean for
+ * then the persistent kernel is launched on `stream` (no graph).  Jobs, arenas, len_dev and status_dev mean what they mean for
  * lsb_plan_create(op) + lsb_plan_run, and the results are identical.
  * At most LSB_STATIC_MAX_JOBS jobs: more is LSB_E_ARG (use a plan).  Every
  * call on one device shares that device's table: calls on one stream run in

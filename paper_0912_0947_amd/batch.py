@@ -66,7 +66,7 @@ _WORD = (torch.int32, torch.uint32) if hasattr(torch, "uint32") else (torch.int3
 
 class Plan:
     """Owns an lsb_plan: a device job table, its pinned host mirror and the
-    HIP graph {table upload, prologue, persistent kernel}.  Before each run
+    HIP graph {table upload, persistent kernel}.  Before each run
     the binding checks that the arenas hold every byte the jobs name and
     that the status and length arrays have an entry per job (the C call
     takes base pointers only and trusts the caller on this)."""

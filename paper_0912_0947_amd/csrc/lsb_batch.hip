@@ -13,9 +13,11 @@
 // spread over many jobs (the frames of a clip).
 //
 // Graph of one run: {H2D copy of the job table from pinned host memory,
-// prologue kernel (per-job status; header decode for extract jobs),
-// persistent kernel}.  The graph is built once per plan; later runs only
-// update the copy size and kernel arguments in the executable graph.
+// persistent kernel}.  The kernel also reports each job's status (and, for
+// extract jobs, the decoded length), and its last block resets the tile
+// counter, so a run whose table is already on the device is the kernel
+// alone.  The graph is built once per plan; later runs only update the copy
+// size and kernel arguments in the executable graph.
 #include <stddef.h>
 #include <string.h>
 
@@ -25,39 +27,6 @@
 #include "lsb_batch_device.hpp"
 
 namespace lsb {
-
-// Prologue: one wave per job writes the job's status (and decoded length);
-// thread 0 resets the persistent kernel's tile counter, which the kernel
-// after it reads (stream order), so a run whose job table is already on the
-// device needs no upload.
-__global__ void __launch_bounds__(256)
-    lsb_batch_prologue(const PlanHeader *hdr, const DevJob *jobs, const uint8_t *stego_arena, uint32_t *len_dev,
-                       int32_t *status_dev) {
-    const uint32_t lane = threadIdx.x & 63u;
-    if (blockIdx.x == 0 && threadIdx.x == 0) const_cast<PlanHeader *>(hdr)->next_tile = 0;
-    const uint64_t n_jobs = hdr->n_jobs;
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    for (uint64_t j = wave; j < n_jobs; j += n_waves) {
-        const DevJob J = jobs[j];
-        uint32_t len = J.len;
-        int status = J.status;
-        if (J.op == LSB_OP_EXTRACT && !J.raw && status == LSB_OK) {
-            len = 0;
-            status = LSB_E_HEADER;
-            if ((uint64_t)J.k * J.n >= 32) {
-                len = decode_header(stego_arena + J.stego_off, J.k, lane);
-                if (4 + (uint64_t)len > room_bytes(J.n, J.k)) status = LSB_E_HEADER;
-                else if ((uint64_t)len > J.cap_bits) status = LSB_E_BUFFER;
-                else status = LSB_OK;
-            }
-        }
-        if (lane == 0) {
-            if (len_dev) len_dev[j] = len;
-            status_dev[j] = status;
-        }
-    }
-}
 
 // Kernel for a launch shape, plan class and raw-slice support.
 static BatchFn batch_fn(int unroll, int nt, int cls, bool raw) {
@@ -103,7 +72,7 @@ struct lsb_plan {
     // graph state
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t copy_node = nullptr, pro_node = nullptr, main_node = nullptr;
+    hipGraphNode_t copy_node = nullptr, main_node = nullptr;
     struct Args {
         const PlanHeader *hdr;
         const DevJob *jobs;
@@ -116,7 +85,7 @@ struct lsb_plan {
     lsb_launch_cfg cfg{};
     int64_t tile_vectors = 0;
     size_t graph_copy_bytes = 0;
-    unsigned main_grid = 0, pro_grid = 0;
+    unsigned main_grid = 0;
     BatchFn fn = nullptr;
 };
 
@@ -127,26 +96,17 @@ static void destroy_graph(lsb_plan *p) {
     p->graph = nullptr;
 }
 
-static void fill_kernel_params(lsb_plan *p, void **argv, hipKernelNodeParams &kp, bool main) {
+static void fill_kernel_params(lsb_plan *p, void **argv, hipKernelNodeParams &kp) {
     argv[0] = &p->args.hdr;
     argv[1] = &p->args.jobs;
-    if (main) {
-        argv[2] = &p->args.cover;
-        argv[3] = &p->args.stego;
-        argv[4] = &p->args.msg;
-        argv[5] = &p->args.len;
-        argv[6] = &p->args.status;
-        kp.func = (void *)p->fn;
-        kp.gridDim = dim3(p->main_grid);
-        kp.blockDim = dim3(p->cfg.block);
-    } else {
-        argv[2] = &p->args.stego;
-        argv[3] = &p->args.len;
-        argv[4] = &p->args.status;
-        kp.func = (void *)lsb_batch_prologue;
-        kp.gridDim = dim3(p->pro_grid);
-        kp.blockDim = dim3(256);
-    }
+    argv[2] = &p->args.cover;
+    argv[3] = &p->args.stego;
+    argv[4] = &p->args.msg;
+    argv[5] = &p->args.len;
+    argv[6] = &p->args.status;
+    kp.func = (void *)p->fn;
+    kp.gridDim = dim3(p->main_grid);
+    kp.blockDim = dim3(p->cfg.block);
     kp.kernelParams = argv;
     kp.extra = nullptr;
     kp.sharedMemBytes = 0;
@@ -154,10 +114,9 @@ static void fill_kernel_params(lsb_plan *p, void **argv, hipKernelNodeParams &kp
 
 // Build (first run) or update the executable graph for the current state.
 static int prepare_graph(lsb_plan *p) {
-    void *main_argv[7], *pro_argv[5];
-    hipKernelNodeParams main_kp{}, pro_kp{};
-    fill_kernel_params(p, main_argv, main_kp, true);
-    fill_kernel_params(p, pro_argv, pro_kp, false);
+    void *main_argv[7];
+    hipKernelNodeParams main_kp{};
+    fill_kernel_params(p, main_argv, main_kp);
     hipError_t e;
     if (!p->exec) {
         e = hipGraphCreate(&p->graph, 0);
@@ -165,9 +124,7 @@ static int prepare_graph(lsb_plan *p) {
         e = hipGraphAddMemcpyNode1D(&p->copy_node, p->graph, nullptr, 0, p->dev, p->host, p->used_bytes,
                                     hipMemcpyHostToDevice);
         if (e != hipSuccess) return destroy_graph(p), hip_fail(e, "hipGraphAddMemcpyNode1D");
-        e = hipGraphAddKernelNode(&p->pro_node, p->graph, &p->copy_node, 1, &pro_kp);
-        if (e != hipSuccess) return destroy_graph(p), hip_fail(e, "hipGraphAddKernelNode(prologue)");
-        e = hipGraphAddKernelNode(&p->main_node, p->graph, &p->pro_node, 1, &main_kp);
+        e = hipGraphAddKernelNode(&p->main_node, p->graph, &p->copy_node, 1, &main_kp);
         if (e != hipSuccess) return destroy_graph(p), hip_fail(e, "hipGraphAddKernelNode(persistent)");
         e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
         if (e != hipSuccess) return destroy_graph(p), hip_fail(e, "hipGraphInstantiate");
@@ -180,8 +137,6 @@ static int prepare_graph(lsb_plan *p) {
         if (e != hipSuccess) return hip_fail(e, "hipGraphExecMemcpyNodeSetParams1D");
         p->graph_copy_bytes = p->used_bytes;
     }
-    e = hipGraphExecKernelNodeSetParams(p->exec, p->pro_node, &pro_kp);
-    if (e != hipSuccess) return hip_fail(e, "hipGraphExecKernelNodeSetParams(prologue)");
     e = hipGraphExecKernelNodeSetParams(p->exec, p->main_node, &main_kp);
     if (e != hipSuccess) return hip_fail(e, "hipGraphExecKernelNodeSetParams(persistent)");
     return LSB_OK;
@@ -278,7 +233,7 @@ static TableInfo fill_table(const lsb_job *jobs, int n_jobs, int op_mode, int64_
         D.n = J.n;
         D.raw = (J.flags & LSB_JOB_RAW) ? 1 : 0;
         t.has_raw |= D.raw != 0;
-        D.len = D.raw ? 0 : J.len;  // what the prologue reports in len_dev
+        D.len = D.raw ? 0 : J.len;  // what the kernel reports in len_dev
         D.k = J.k;
         D.op = op;
         D.tile_begin = tiles;
@@ -345,17 +300,11 @@ static TableInfo fill_table(const lsb_job *jobs, int n_jobs, int op_mode, int64_
     return t;
 }
 
-// Grids of the persistent kernel (capped at blocks_per_cu blocks per CU,
-// never more blocks than tiles) and of the prologue (one wave per job, 4
-// waves per block).
+// Grid of the persistent kernel: capped at blocks_per_cu blocks per CU,
+// never more blocks than tiles.
 static unsigned main_grid_for(const lsb_launch_cfg &cfg, uint64_t total_tiles) {
     const uint64_t cap_blocks = (uint64_t)(cfg.blocks_per_cu > 0 ? cfg.blocks_per_cu : 8) * (uint64_t)device_cus();
     return (unsigned)(total_tiles < cap_blocks ? (total_tiles ? total_tiles : 1) : cap_blocks);
-}
-
-static unsigned prologue_grid_for(int n_jobs) {
-    const uint64_t g = ceil_div((uint64_t)n_jobs, 4);
-    return (unsigned)(g > 4096 ? 4096 : (g ? g : 1));
 }
 
 static int64_t batch_tile_vectors() {
@@ -502,7 +451,6 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
     p->cfg = cfg;
     p->fn = fn;
     p->main_grid = main_grid_for(cfg, p->total_tiles);
-    p->pro_grid = prologue_grid_for(p->n_jobs);
     p->args.hdr = (const PlanHeader *)p->dev;
     p->args.jobs = (const DevJob *)(p->dev + sizeof(PlanHeader));
     p->args.cover = cover_arena;
@@ -520,7 +468,7 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
         if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent(plan)");
     }
     // upload the job table only when it changed since the last upload (the
-    // prologue resets the tile counter either way)
+    // kernel's last block resets the tile counter either way)
     e = hipGraphNodeSetEnabled(p->exec, p->copy_node, p->table_dirty ? 1 : 0);
     if (e != hipSuccess) return hip_fail(e, "hipGraphNodeSetEnabled(table upload)");
     e = hipGraphLaunch(p->exec, (hipStream_t)stream);
@@ -614,10 +562,6 @@ int lsb_batch_run_static(const lsb_job *jobs, int n_jobs, int op, const uint8_t 
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(static job table)");
     const PlanHeader *hdr = (const PlanHeader *)table;
     const DevJob *dj = (const DevJob *)(table + sizeof(PlanHeader));
-    void *pro_args[] = {&hdr, &dj, &stego_arena, &len_dev, &status_dev};
-    e = hipLaunchKernel((const void *)lsb_batch_prologue, dim3(prologue_grid_for(n_jobs)), dim3(256), pro_args, 0,
-                        st);
-    if (e != hipSuccess) return hip_fail(e, "prologue launch");
     const BatchFn fn = batch_fn(cfg.unroll, cfg.nontemporal, t.cls, t.has_raw);
     void *main_args[] = {&hdr, &dj, &cover_arena, &stego_arena, &msg_arena, &len_dev, &status_dev};
     e = hipLaunchKernel((const void *)fn, dim3(main_grid_for(cfg, t.tiles)), dim3(cfg.block), main_args, 0, st);

@@ -13,17 +13,22 @@ namespace lsb {
 
 // The tile counter has a 128-byte cache line of its own: sharing a line with
 // the job records that every block reads made each atomic contend with those
-// reads (a one-job batch ran at 40 % of a many-job batch).
+// reads (a one-job batch ran at 40 % of a many-job batch).  Both counters
+// are zero in an uploaded table, and the last block of each run sets them
+// back to zero, so a run whose table is already on the device starts from
+// zero without an upload.
 struct PlanHeader {
     uint64_t n_jobs;
     uint64_t total_tiles;
     uint64_t tile_vectors;
     uint64_t pad0[13];
-    uint64_t next_tile;  // tile counter of the persistent kernel; the upload resets it to 0
-    uint64_t pad1[15];
+    uint64_t next_tile;    // tile counter of the persistent kernel
+    uint64_t blocks_done;  // blocks whose producer has taken its last tile id this run
+    uint64_t pad1[14];
 };
-static_assert(sizeof(PlanHeader) == 256 && offsetof(PlanHeader, next_tile) == 128,
-              "counter on its own line, job records 256-byte aligned");
+static_assert(sizeof(PlanHeader) == 256 && offsetof(PlanHeader, next_tile) == 128 &&
+                  offsetof(PlanHeader, blocks_done) == 136,
+              "counters on their own line, job records 256-byte aligned");
 
 struct DevJob {
     uint64_t cover_off, stego_off, msg_off, n;
@@ -156,8 +161,11 @@ constexpr int batch_min_waves() {
 // streaming itself: it takes the next tile id from the plan's counter,
 // resolves the tile's job (forward search over the tile prefix, 64 jobs per
 // ballot; jobs only move forward as the tile id grows), reads the job record
-// and the job's device status, and publishes all of it in a slot of a
-// two-slot LDS ring.  The other waves (the workers) read their next tile
+// (and, for a header extract job, decodes the job's length header), and
+// publishes all of it in a slot of a two-slot LDS ring.  The producer that
+// takes a job's first tile also reports the job's length and status; jobs
+// without tiles are reported by a sweep over the job table that every
+// producer runs once.  The other waves (the workers) read their next tile
 // from the ring when they finish the current one, so they never wait for
 // each other at a tile boundary, and the latency of the counter, the search
 // and the record reads is spent by the producer while the workers stream.
@@ -210,6 +218,67 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
     return ((uint64_t)uniform32((uint32_t)(v >> 32)) << 32) | uniform32((uint32_t)v);
 }
 
+// What a job reports in len_dev / status_dev.  The host-validated status
+// and length, except for a header extract job that the host let through:
+// its length is the stego's 32-bit header (Section VII, the stream's first
+// 32 bits), which must fit the cover's room and the job's output buffer.
+// J is wave-uniform: the decode spreads the header's bits over the lanes.
+struct JobReport {
+    uint32_t len;
+    int32_t status;
+};
+
+__device__ __forceinline__ JobReport job_report(const DevJob &J, const uint8_t *stego_arena, uint32_t lane) {
+    JobReport r{J.len, J.status};
+    if (J.op == LSB_OP_EXTRACT && !J.raw && J.status == LSB_OK) {
+        r.len = 0;
+        r.status = LSB_E_HEADER;
+        if ((uint64_t)J.k * J.n >= 32) {
+            r.len = decode_header(stego_arena + J.stego_off, J.k, lane);
+            if (4 + (uint64_t)r.len > room_bytes(J.n, J.k)) r.status = LSB_E_HEADER;
+            else if ((uint64_t)r.len > J.cap_bits) r.status = LSB_E_BUFFER;
+            else r.status = LSB_OK;
+        }
+    }
+    return r;
+}
+
+// Reports of the jobs without tiles (refused on the host, empty slices, and
+// header extract jobs whose cover holds fewer than 32 bits), lane-parallel
+// over the table: block b's producer takes jobs 64b + lane, then every
+// 64 G-th.  No tile is ever handed out for these jobs, so nothing else
+// writes their entries.  A header extract job the host let through has a
+// tile whenever k n >= 32, so one without tiles is refused here.
+__device__ __forceinline__ void report_empty_jobs(const DevJob *jobs, uint64_t n_jobs, uint32_t *len_dev,
+                                                  int32_t *status_dev, uint32_t lane) {
+    for (uint64_t j = (uint64_t)blockIdx.x * 64 + lane; j < n_jobs; j += (uint64_t)gridDim.x * 64) {
+        const DevJob &J = jobs[j];
+        if (J.tile_begin != jobs[j + 1].tile_begin) continue;  // the producer of its first tile reports it
+        uint32_t len = J.len;
+        int32_t status = J.status;
+        if (J.op == LSB_OP_EXTRACT && !J.raw && status == LSB_OK) {
+            len = 0;
+            status = LSB_E_HEADER;
+        }
+        if (len_dev) len_dev[j] = len;
+        status_dev[j] = status;
+    }
+}
+
+// A producer is done with the counter (lane 0): the last one of the grid
+// sets both counters back to zero for the plan's next run.  Every producer
+// has taken its last tile id before it counts itself (its atomics return
+// values that it has used), so after the last count nothing else touches
+// the counters in this run.
+__device__ __forceinline__ void producer_done(const PlanHeader *hdr) {
+    PlanHeader *h = const_cast<PlanHeader *>(hdr);
+    const unsigned long long before = atomicAdd((unsigned long long *)&h->blocks_done, 1ull);
+    if (before == (unsigned long long)gridDim.x - 1) {
+        __hip_atomic_store(&h->next_tile, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&h->blocks_done, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // Persistent kernel: tiles come from one counter in arrival order, so the
 // tiles in flight at any moment are neighbours in the arenas (a static b,
 // b + G, ... order lets blocks drift apart over the run).  Blocks have at
@@ -217,7 +286,7 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
 template <int UNR, bool NT, int CLS, bool RAW>
 __global__ void __launch_bounds__(1024, (batch_min_waves<UNR, CLS, RAW>()))
     lsb_batch_kernel(const PlanHeader *hdr, const DevJob *jobs, const uint8_t *cover_arena, uint8_t *stego_arena,
-                     uint8_t *msg_arena, const uint32_t *len_dev, const int32_t *status_dev) {
+                     uint8_t *msg_arena, uint32_t *len_dev, int32_t *status_dev) {
     __shared__ TileSlot ring[kRing];
     __shared__ uint32_t seq[kRing];      // iteration whose tile the slot holds
     __shared__ uint32_t readers[kRing];  // workers that have read the slot's current content
@@ -242,6 +311,7 @@ __global__ void __launch_bounds__(1024, (batch_min_waves<UNR, CLS, RAW>()))
             t = uniform64(t);
             const uint32_t sl = m % kRing;
             uint32_t run = 0, len = 0;
+            DevJob J{};
             if (t < total) {
                 // largest j with jobs[j].tile_begin <= t (entry n_jobs holds total > t)
                 for (;;) {
@@ -253,16 +323,22 @@ __global__ void __launch_bounds__(1024, (batch_min_waves<UNR, CLS, RAW>()))
                     if (cnt < 64) break;
                 }
                 j = uniform64(j);
-                run = jobs[j].status == LSB_OK;
-                if (run && jobs[j].op == LSB_OP_EXTRACT && !(RAW && jobs[j].raw)) {
-                    run = status_dev[j] == LSB_OK;
-                    len = len_dev[j];
+                J = jobs[j];
+                const JobReport r = job_report(J, stego_arena, lane);
+                run = r.status == LSB_OK;
+                len = r.len;
+                if (t == J.tile_begin && lane == 0) {  // the job's first tile: report the job
+                    if (len_dev) len_dev[j] = r.len;
+                    status_dev[j] = r.status;
                 }
             }
             // every worker must have taken tile m - 1 (and so every earlier one)
-            if (m && !lds_wait_eq(&readers[(m - 1) % kRing], workers)) return;
+            if (m && !lds_wait_eq(&readers[(m - 1) % kRing], workers)) {
+                if (lane == 0) producer_done(hdr);
+                return;
+            }
             if (lane == 0) {
-                if (t < total) ring[sl].job = jobs[j];
+                if (t < total) ring[sl].job = J;
                 ring[sl].tile = t;
                 ring[sl].len = len;
                 ring[sl].run = run;
@@ -270,7 +346,12 @@ __global__ void __launch_bounds__(1024, (batch_min_waves<UNR, CLS, RAW>()))
                 lds_order();
                 lds_write(&seq[sl], m);
             }
-            if (t >= total) return;  // the end mark is out
+            // after the first hand-off, so that the workers start at once
+            if (m == 0) report_empty_jobs(jobs, n_jobs, len_dev, status_dev, lane);
+            if (t >= total) {  // the end mark is out
+                if (lane == 0) producer_done(hdr);
+                return;
+            }
             if (lane == 0) t = atomicAdd(counter, 1ull);
         }
     }
@@ -305,8 +386,8 @@ __global__ void __launch_bounds__(1024, (batch_min_waves<UNR, CLS, RAW>()))
     }
 }
 
-typedef void (*BatchFn)(const PlanHeader *, const DevJob *, const uint8_t *, uint8_t *, uint8_t *, const uint32_t *,
-                        const int32_t *);
+typedef void (*BatchFn)(const PlanHeader *, const DevJob *, const uint8_t *, uint8_t *, uint8_t *, uint32_t *,
+                        int32_t *);
 
 // Kernel table of one launch shape: entry CLS of the class sequence.
 template <int UNR, bool NT, bool RAW, int... C>

@@ -221,9 +221,8 @@ class HipExecutor : public Executor {
    private:
     struct S;
     // A launch of at most kDirectMax jobs issues them through the plain entry
-    // points, one kernel each, instead of a plan (no table upload, prologue
-    // or graph): a plan's host-side cost is that of about five plain
-    // launches.  Results and statuses are those a plan reports.  An embed
+    // points, one kernel each, instead of a plan (no table upload or graph):
+    // a plan's host-side cost is that of about five plain launches.  Results and statuses are those a plan reports.  An embed
     // over capacity is refused on the host and its status set here; extracts
     // report decoded lengths and statuses on the device, in the same places
     // as a plan's, and one copy brings them back.

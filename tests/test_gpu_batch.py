@@ -388,6 +388,46 @@ def test_in_place_and_empty_plans():
         plan.close()
 
 
+def test_reruns_of_an_unchanged_table():
+    """While a plan's job table is unchanged its runs upload nothing, so each
+    run starts from the tile counter that the previous run's last block set
+    back to zero.  Four rounds on new messages in one layout: every embed
+    gives the oracle's stego, and the extract plan run after it reports
+    every length and message."""
+    wl = BatchWorkload(24, oracle.capacity, seed=437, lo=64, hi=3000)
+    cover, stego, msg, out = wl.allocate(DEV)
+    st_e = torch.empty(wl.count, dtype=torch.int32, device=DEV)
+    st_x = torch.empty(wl.count, dtype=torch.int32, device=DEV)
+    lens = torch.empty(wl.count, dtype=torch.int32, device=DEV)
+    cover_h = to_host(cover)
+    pe = batch.Plan(wl.count, OP_EMBED, wl.jobs(OP_EMBED))
+    px = batch.Plan(wl.count, OP_EXTRACT, wl.jobs(OP_EXTRACT))
+    try:
+        for rep in range(4):
+            inputs.fill_uniform(msg, 600 + rep)
+            st_e.fill_(99)
+            st_x.fill_(99)
+            lens.fill_(-1)
+            stego.zero_()
+            out.zero_()
+            pe.embed_batch(cover, stego, msg, st_e)
+            px.extract_batch(stego, out, lens, st_x)
+            torch.cuda.synchronize()
+            assert bool((st_e == OK).all()) and bool((st_x == OK).all()), rep
+            assert np.array_equal(lens.cpu().numpy(), wl.len), rep
+            stego_h, msg_h, out_h = to_host(stego), to_host(msg), to_host(out)
+            for i in range(wl.count):
+                o, n, k = int(wl.cover_off[i]), int(wl.n[i]), int(wl.k[i])
+                m0, ln = int(wl.msg_off[i]), int(wl.len[i])
+                rc, want = oracle.embed(cover_h[o:o + n], msg_h[m0:m0 + ln], k)
+                assert rc == 0
+                assert_bytes_equal(stego_h[o:o + n], want, "run %d job %d stego" % (rep, i))
+                assert_bytes_equal(out_h[m0:m0 + ln], msg_h[m0:m0 + ln], "run %d job %d message" % (rep, i))
+    finally:
+        pe.close()
+        px.close()
+
+
 def test_binding_refuses_buffers_the_jobs_do_not_fit():
     """The C call takes arena base pointers only; the binding checks, before
     anything is enqueued, that every arena holds the bytes its jobs name and
