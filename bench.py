@@ -106,7 +106,7 @@ def stored_batch_traffic(launch: str):
 
 def batched_roofline(bytes_, seconds, launch, clock):
     """Achieved GB/s of one batched launch (algorithmic bytes over `seconds`,
-    measured by `clock`: "stream events" around the graph launch, or "wall"
+    measured by `clock`: "stream events" around the plan's run, or "wall"
     including the host's enqueue), its fraction of the 8 TB/s HBM peak, and
     its counter traffic if the profile is current."""
     achieved = bytes_ / seconds / 1e9
@@ -237,7 +237,7 @@ def cpu_baseline_threads(cover_np, msgs, threads, min_seconds=1.5, max_steps=4):
 
 
 def bench_batched(api, batch, dev, log_fn, reps=3):
-    """Uneven batch of 4096 covers (about 35 GB): one persistent graph launch
+    """Uneven batch of 4096 covers (about 35 GB): one persistent launch
     per op against a loop of one plain launch per cover on one stream."""
     import ctypes
 

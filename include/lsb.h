@@ -62,7 +62,7 @@ enum {
     LSB_E_HEADER = -3,   /* decoded length does not fit the stego cover */
     LSB_E_BUFFER = -4,   /* decoded length exceeds the output buffer */
     LSB_E_HIP = -5,      /* a HIP runtime call failed */
-    LSB_E_NOMEM = -6     /* a plan or graph could not be allocated */
+    LSB_E_NOMEM = -6     /* a plan could not be allocated */
 };
 
 enum { LSB_OP_EMBED = 0, LSB_OP_EXTRACT = 1, LSB_OP_MIXED = 2 };
@@ -263,9 +263,9 @@ typedef struct lsb_plan lsb_plan;
 
 /* Create a plan for n_jobs jobs (1 <= n_jobs <= 2^24).  Allocates device and
  * pinned host memory (this is the only allocating call of the batched form).
- * The plan owns a HIP graph {job-table upload, persistent kernel} built on
- * the first run and reused afterwards (the upload only runs while the table
- * has changed since the last one).
+ * A run is an asynchronous upload of the job table from the plan's pinned
+ * mirror (only when the table changed since the last upload), then one
+ * persistent kernel launch.
  *   jobs_host  host array of n_jobs jobs, or NULL to reserve room for n_jobs
  *              jobs and set them later with lsb_plan_update.
  *   op         LSB_OP_EMBED or LSB_OP_EXTRACT: every job of the plan is of
@@ -275,7 +275,7 @@ typedef struct lsb_plan lsb_plan;
 int lsb_plan_create(lsb_plan **plan, const lsb_job *jobs_host, int n_jobs, int op);
 
 /* Replace the plan's job list (n_jobs <= the n_jobs given at creation),
- * keeping its graph.  Validates every job on the host: a job with bad k,
+ * keeping its memory.  Validates every job on the host: a job with bad k,
  * offsets, flags or raw-slice alignment is LSB_E_ARG for the whole call; a
  * header embed job whose len exceeds its
  * capacity is not an error of the call: it gets status LSB_E_CAPACITY and no

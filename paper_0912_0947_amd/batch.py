@@ -1,5 +1,5 @@
-"""Batched embed/extract: many covers of uneven size and k in one persistent,
-graph-replayed launch (lsb_plan_* in include/lsb.h).  Marshalling only."""
+"""Batched embed/extract: many covers of uneven size and k in one persistent
+launch (lsb_plan_* in include/lsb.h).  Marshalling only."""
 from __future__ import annotations
 
 import ctypes
@@ -65,8 +65,9 @@ _WORD = (torch.int32, torch.uint32) if hasattr(torch, "uint32") else (torch.int3
 
 
 class Plan:
-    """Owns an lsb_plan: a device job table, its pinned host mirror and the
-    HIP graph {table upload, persistent kernel}.  Before each run
+    """Owns an lsb_plan: a device job table and its pinned host mirror (a
+    run uploads the table when it changed, then launches the persistent
+    kernel).  Before each run
     the binding checks that the arenas hold every byte the jobs name and
     that the status and length arrays have an entry per job (the C call
     takes base pointers only and trusts the caller on this)."""

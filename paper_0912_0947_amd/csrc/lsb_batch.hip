@@ -1,5 +1,5 @@
 // lsb_batch.hip -- batched embed/extract over thousands of covers of uneven
-// size and k in one persistent launch, replayed through a HIP graph.
+// size and k in one persistent launch.
 //
 // The paper loops on the host over the rows of an image (Section VI steps
 // 4-5 split the data across rows; Section VII steps 3-4 likewise), paying a
@@ -12,12 +12,14 @@
 // slice [t0, t0 + n) of a longer logical cover; slices of one stream may be
 // spread over many jobs (the frames of a clip).
 //
-// Graph of one run: {H2D copy of the job table from pinned host memory,
-// persistent kernel}.  The kernel also reports each job's status (and, for
+// One run: an asynchronous copy of the job table from the plan's pinned
+// host mirror, only when the table changed since the last upload, then the
+// persistent kernel.  The kernel also reports each job's status (and, for
 // extract jobs, the decoded length), and its last block resets the tile
-// counter, so a run whose table is already on the device is the kernel
-// alone.  The graph is built once per plan; later runs only update the copy
-// size and kernel arguments in the executable graph.
+// counter, so a run whose table is already on the device is one kernel
+// launch.  (While a prologue kernel ran before the persistent one, the run
+// was a HIP graph of three nodes; with one kernel left, launching the graph
+// cost about 25 us more host time per run than launching the kernel.)
 #include <stddef.h>
 #include <string.h>
 
@@ -69,78 +71,8 @@ struct lsb_plan {
     hipStream_t last_stream = nullptr;  // stream of the last run
     bool ran = false;
     bool table_dirty = true;  // the host table changed since the last upload
-    // graph state
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipGraphNode_t copy_node = nullptr, main_node = nullptr;
-    struct Args {
-        const PlanHeader *hdr;
-        const DevJob *jobs;
-        const uint8_t *cover;
-        uint8_t *stego;
-        uint8_t *msg;
-        uint32_t *len;
-        int32_t *status;
-    } args{};
-    lsb_launch_cfg cfg{};
-    int64_t tile_vectors = 0;
-    size_t graph_copy_bytes = 0;
-    unsigned main_grid = 0;
-    BatchFn fn = nullptr;
+    int64_t tile_vectors = 0;  // tile size the table was filled with
 };
-
-static void destroy_graph(lsb_plan *p) {
-    if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
-    p->exec = nullptr;
-    p->graph = nullptr;
-}
-
-static void fill_kernel_params(lsb_plan *p, void **argv, hipKernelNodeParams &kp) {
-    argv[0] = &p->args.hdr;
-    argv[1] = &p->args.jobs;
-    argv[2] = &p->args.cover;
-    argv[3] = &p->args.stego;
-    argv[4] = &p->args.msg;
-    argv[5] = &p->args.len;
-    argv[6] = &p->args.status;
-    kp.func = (void *)p->fn;
-    kp.gridDim = dim3(p->main_grid);
-    kp.blockDim = dim3(p->cfg.block);
-    kp.kernelParams = argv;
-    kp.extra = nullptr;
-    kp.sharedMemBytes = 0;
-}
-
-// Build (first run) or update the executable graph for the current state.
-static int prepare_graph(lsb_plan *p) {
-    void *main_argv[7];
-    hipKernelNodeParams main_kp{};
-    fill_kernel_params(p, main_argv, main_kp);
-    hipError_t e;
-    if (!p->exec) {
-        e = hipGraphCreate(&p->graph, 0);
-        if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
-        e = hipGraphAddMemcpyNode1D(&p->copy_node, p->graph, nullptr, 0, p->dev, p->host, p->used_bytes,
-                                    hipMemcpyHostToDevice);
-        if (e != hipSuccess) return destroy_graph(p), hip_fail(e, "hipGraphAddMemcpyNode1D");
-        e = hipGraphAddKernelNode(&p->main_node, p->graph, &p->copy_node, 1, &main_kp);
-        if (e != hipSuccess) return destroy_graph(p), hip_fail(e, "hipGraphAddKernelNode(persistent)");
-        e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) return destroy_graph(p), hip_fail(e, "hipGraphInstantiate");
-        p->graph_copy_bytes = p->used_bytes;
-        return LSB_OK;
-    }
-    if (p->graph_copy_bytes != p->used_bytes) {
-        e = hipGraphExecMemcpyNodeSetParams1D(p->exec, p->copy_node, p->dev, p->host, p->used_bytes,
-                                              hipMemcpyHostToDevice);
-        if (e != hipSuccess) return hip_fail(e, "hipGraphExecMemcpyNodeSetParams1D");
-        p->graph_copy_bytes = p->used_bytes;
-    }
-    e = hipGraphExecKernelNodeSetParams(p->exec, p->main_node, &main_kp);
-    if (e != hipSuccess) return hip_fail(e, "hipGraphExecKernelNodeSetParams(persistent)");
-    return LSB_OK;
-}
 
 // ---------------------------------------------------------------------------
 // Table of lsb_batch_run_static: the job table and tile counter live in this
@@ -436,53 +368,42 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
     int64_t tv;
     const lsb_launch_cfg cfg = batch_cfg_for(p->has_embed, p->has_extract, &tv);
     if (tv != p->tile_vectors) return fail(LSB_E_ARG, "lsb_plan_run: tile size changed since lsb_plan_update");
-    // a different kernel (shape or job class) cannot be swapped into the
-    // executable graph: rebuild it
     const BatchFn fn = batch_fn(cfg.unroll, cfg.nontemporal, p->cls, p->has_raw);
-    const bool rebuild = p->exec && (cfg.block != p->cfg.block || fn != p->fn);
-    if (rebuild) {
-        // the previous launch of the old graph must be finished before it goes
-        if (p->ran) {
-            const hipError_t se = hipEventSynchronize(p->done);
-            if (se != hipSuccess) return hip_fail(se, "hipEventSynchronize(plan)");
-        }
-        destroy_graph(p);
-    }
-    p->cfg = cfg;
-    p->fn = fn;
-    p->main_grid = main_grid_for(cfg, p->total_tiles);
-    p->args.hdr = (const PlanHeader *)p->dev;
-    p->args.jobs = (const DevJob *)(p->dev + sizeof(PlanHeader));
-    p->args.cover = cover_arena;
-    p->args.stego = stego_arena;
-    p->args.msg = msg_arena;
-    p->args.len = len_dev;
-    p->args.status = status_dev;
-    int rc = prepare_graph(p);
-    if (rc != LSB_OK) return rc;
+    const PlanHeader *hdr = (const PlanHeader *)p->dev;
+    const DevJob *jobs = (const DevJob *)(p->dev + sizeof(PlanHeader));
+    hipStream_t st = (hipStream_t)stream;
     hipError_t e;
-    if (p->ran && (hipStream_t)stream != p->last_stream) {
-        // every run shares the device job table and its tile counter: a run
+    if (p->ran && st != p->last_stream) {
+        // every run shares the device job table and its tile counters: a run
         // on another stream starts only after the previous run has finished
-        e = hipStreamWaitEvent((hipStream_t)stream, p->done, 0);
+        e = hipStreamWaitEvent(st, p->done, 0);
         if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent(plan)");
     }
     // upload the job table only when it changed since the last upload (the
-    // kernel's last block resets the tile counter either way)
-    e = hipGraphNodeSetEnabled(p->exec, p->copy_node, p->table_dirty ? 1 : 0);
-    if (e != hipSuccess) return hip_fail(e, "hipGraphNodeSetEnabled(table upload)");
-    e = hipGraphLaunch(p->exec, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-    e = hipEventRecord(p->done, (hipStream_t)stream);
+    // kernel's last block resets the tile counters either way)
+    const bool upload = p->table_dirty;
+    if (upload) {
+        e = hipMemcpyAsync(p->dev, p->host, p->used_bytes, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(job table)");
+    }
+    void *argv[] = {&hdr, &jobs, &cover_arena, &stego_arena, &msg_arena, &len_dev, &status_dev};
+    e = hipLaunchKernel((const void *)fn, dim3(main_grid_for(cfg, p->total_tiles)), dim3(cfg.block), argv, 0, st);
+    if (e != hipSuccess) {
+        // an enqueued upload still reads the pinned mirror: let it finish
+        // before a later update may refill the mirror
+        if (upload) (void)hipStreamSynchronize(st);
+        return hip_fail(e, "persistent kernel launch");
+    }
+    e = hipEventRecord(p->done, st);
     if (e != hipSuccess) {
         // without the event nothing tracks the launch: wait for it here so
         // that a later update or destroy cannot overtake it
-        (void)hipStreamSynchronize((hipStream_t)stream);
+        (void)hipStreamSynchronize(st);
         return hip_fail(e, "hipEventRecord(plan)");
     }
     p->ran = true;
     p->table_dirty = false;
-    p->last_stream = (hipStream_t)stream;
+    p->last_stream = st;
     return LSB_OK;
 }
 
@@ -510,7 +431,6 @@ void lsb_plan_destroy(lsb_plan *p) {
     if (!p) return;
     // teardown: nothing useful can be done with a failure here
     if (p->ran) (void)hipEventSynchronize(p->done);
-    destroy_graph(p);
     if (p->done) (void)hipEventDestroy(p->done);
     if (p->dev) (void)hipFree(p->dev);
     if (p->host) (void)hipHostFree(p->host);

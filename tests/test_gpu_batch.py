@@ -1,4 +1,4 @@
-"""GPU parity of the batched (persistent, graph-replayed) path.
+"""GPU parity of the batched (persistent) path.
 
 Each job's result must equal the oracle's and the single-call result, for
 mixed embed/extract batches with invalid jobs, tiny tiles (many tile
@@ -172,13 +172,13 @@ def test_few_class_mixed_plans(ks, restore_tiles):
     switch): every status, length and output lands at the caller's job
     index, in shuffled orders and with 64-vector tiles; one plan then takes
     job lists of one class (its specialised kernel), two classes and all of
-    them in turn, its graph rebuilt at each change of kernel."""
+    them in turn, its kernel changing with the class."""
     jobs = _mixed_batch(48, 2500 + len(ks), ks=ks)
     assert len({(j["op"], j["k"]) for j in jobs}) == 2 * len(ks)
     _run_and_check(jobs, order=inputs.rng(2510).permutation(len(jobs)))
     batch.set_tile_vectors(64)
     _run_and_check(jobs, order=inputs.rng(2511).permutation(len(jobs)))
-    # one plan, job lists of one class, two classes, then all of them (graphs rebuilt)
+    # one plan, job lists of one class, two classes, then all of them
     plan = batch.Plan(len(jobs))
     try:
         for sub in ([j for j in jobs if j["k"] == ks[0] and j["op"] == OP_EMBED],
@@ -208,7 +208,7 @@ def restore_tiles():
 
 
 def test_plan_reuse_across_job_lists(mixed):
-    """One plan, several job lists and sizes: the executable graph is updated
+    """One plan, several job lists and sizes: the device table is replaced
     in place and every run is correct."""
     plan = batch.Plan(len(mixed))
     try:
