@@ -428,6 +428,43 @@ def test_reruns_of_an_unchanged_table():
         px.close()
 
 
+def test_runs_on_alternating_streams_and_shapes(restore_tiles):
+    """Every run of a plan shares its device table and tile counters, so a
+    run on another stream than the previous run's must wait for it.  Four
+    runs are enqueued without a host wait, alternating between two streams,
+    each into its own stego arena, and the embed launch shape changes
+    between the second and third run (another kernel): each arena holds the
+    oracle's stego."""
+    wl = BatchWorkload(40, oracle.capacity, seed=441, lo=16, hi=200)
+    cover, _, msg, _ = wl.allocate(DEV)
+    outs = [torch.zeros_like(cover) for _ in range(4)]
+    sts = [torch.full((wl.count,), 99, dtype=torch.int32, device=DEV) for _ in range(4)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]  # default priority
+    plan = batch.Plan(wl.count, OP_EMBED, wl.jobs(OP_EMBED))
+    torch.cuda.synchronize()
+    try:
+        for r in range(4):
+            if r == 2:
+                batch.tune_set_op(OP_EMBED, 256, 1, 4, 0)
+            plan.embed_batch(cover, outs[r], msg, sts[r], stream=streams[r % 2])
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    cover_h, msg_h = to_host(cover), to_host(msg)
+    want = []
+    for i in range(wl.count):
+        o, n, k = int(wl.cover_off[i]), int(wl.n[i]), int(wl.k[i])
+        m0, ln = int(wl.msg_off[i]), int(wl.len[i])
+        rc, w = oracle.embed(cover_h[o:o + n], msg_h[m0:m0 + ln], k)
+        assert rc == 0
+        want.append((o, n, w))
+    for r in range(4):
+        assert bool((sts[r] == OK).all()), r
+        out_h = to_host(outs[r])
+        for i, (o, n, w) in enumerate(want):
+            assert_bytes_equal(out_h[o:o + n], w, "run %d job %d" % (r, i))
+
+
 def test_binding_refuses_buffers_the_jobs_do_not_fit():
     """The C call takes arena base pointers only; the binding checks, before
     anything is enqueued, that every arena holds the bytes its jobs name and
