@@ -291,9 +291,11 @@ int lsb_plan_update(lsb_plan *plan, const lsb_job *jobs_host, int n_jobs);
  * slices (len_dev may be NULL if the plan has no extract job).  Results are
  * identical to one lsb_embed / lsb_extract call per job (raw slices:
  * lsb_embed_raw / lsb_extract_raw).  The arena base pointers must be
- * 256-byte aligned.  LSB_E_ARG if the current device is not the plan's, or
- * if the batch tile size (lsb_batch_tune_set) changed since the plan's last
- * lsb_plan_update (update the plan again first). */
+ * 256-byte aligned.  LSB_E_ARG if the current device is not the plan's, if
+ * the batch tile size (lsb_batch_tune_set) changed since the plan's last
+ * lsb_plan_update (update the plan again first), or if `stream` is capturing
+ * a graph (a captured run would replay outside the plan's tracking of its
+ * table and runs); nothing is enqueued then. */
 int lsb_plan_run(lsb_plan *plan, const uint8_t *cover_arena,
                  uint8_t *stego_arena, uint8_t *msg_arena, uint32_t *len_dev,
                  int32_t *status_dev, void *stream);

@@ -368,10 +368,20 @@ int lsb_plan_run(lsb_plan *p, const uint8_t *cover_arena, uint8_t *stego_arena, 
     int64_t tv;
     const lsb_launch_cfg cfg = batch_cfg_for(p->has_embed, p->has_extract, &tv);
     if (tv != p->tile_vectors) return fail(LSB_E_ARG, "lsb_plan_run: tile size changed since lsb_plan_update");
+    hipStream_t st = (hipStream_t)stream;
+    // A captured run would replay its upload and kernel outside the plan's
+    // tracking (the upload state, the completion event that updates wait
+    // for, the kernel chosen for the table's class): refused before
+    // anything is enqueued.
+    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+    const hipError_t ce = hipStreamIsCapturing(st, &capture);
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamIsCapturing");
+    if (capture != hipStreamCaptureStatusNone)
+        return fail(LSB_E_ARG, "lsb_plan_run: the stream is capturing a graph (a captured run would replay outside "
+                               "the plan's tracking of its table and runs)");
     const BatchFn fn = batch_fn(cfg.unroll, cfg.nontemporal, p->cls, p->has_raw);
     const PlanHeader *hdr = (const PlanHeader *)p->dev;
     const DevJob *jobs = (const DevJob *)(p->dev + sizeof(PlanHeader));
-    hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     if (p->ran && st != p->last_stream) {
         // every run shares the device job table and its tile counters: a run

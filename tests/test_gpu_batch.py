@@ -9,7 +9,7 @@ import torch
 
 import oracle
 from paper_0912_0947_amd import api, batch, inputs
-from paper_0912_0947_amd._lib import E_BUFFER, E_CAPACITY, E_HEADER, OK, OP_EMBED, OP_EXTRACT
+from paper_0912_0947_amd._lib import E_ARG, E_BUFFER, E_CAPACITY, E_HEADER, OK, OP_EMBED, OP_EXTRACT, LsbError
 from paper_0912_0947_amd.workloads import BatchWorkload
 
 import oracle_pool
@@ -463,6 +463,45 @@ def test_runs_on_alternating_streams_and_shapes(restore_tiles):
         out_h = to_host(outs[r])
         for i, (o, n, w) in enumerate(want):
             assert_bytes_equal(out_h[o:o + n], w, "run %d job %d" % (r, i))
+
+
+def test_plan_refuses_a_capturing_stream():
+    """A plan run under stream capture would replay its table upload and
+    kernel outside the plan's tracking: the call is refused before anything
+    is enqueued, and the same run outside capture gives the oracle's stego."""
+    wl = BatchWorkload(8, oracle.capacity, seed=443, lo=16, hi=64)
+    cover, stego, msg, _ = wl.allocate(DEV)
+    status = torch.full((wl.count,), 99, dtype=torch.int32, device=DEV)
+    mark = torch.zeros(1, dtype=torch.int32, device=DEV)
+    plan = batch.Plan(wl.count, OP_EMBED, wl.jobs(OP_EMBED))
+    side = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    try:
+        with torch.cuda.stream(side):
+            graph.capture_begin()
+            try:
+                mark.add_(1)  # the captured graph is not empty
+                with pytest.raises(LsbError) as e:
+                    plan.embed_batch(cover, stego, msg, status, stream=side)
+            finally:
+                graph.capture_end()
+        assert e.value.code == E_ARG and "capturing" in str(e.value)
+        del graph
+        torch.cuda.synchronize()
+        assert bool((status == 99).all()) and int(mark) == 0, "nothing ran during the capture"
+        plan.embed_batch(cover, stego, msg, status)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    assert bool((status == OK).all())
+    cover_h, stego_h, msg_h = to_host(cover), to_host(stego), to_host(msg)
+    for i in range(wl.count):
+        o, n, k = int(wl.cover_off[i]), int(wl.n[i]), int(wl.k[i])
+        m0, ln = int(wl.msg_off[i]), int(wl.len[i])
+        rc, want = oracle.embed(cover_h[o:o + n], msg_h[m0:m0 + ln], k)
+        assert rc == 0
+        assert_bytes_equal(stego_h[o:o + n], want, "job %d" % i)
 
 
 def test_binding_refuses_buffers_the_jobs_do_not_fit():
