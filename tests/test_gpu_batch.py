@@ -465,6 +465,52 @@ def test_runs_on_alternating_streams_and_shapes(restore_tiles):
             assert_bytes_equal(out_h[o:o + n], w, "run %d job %d" % (r, i))
 
 
+def test_many_jobs_without_tiles():
+    """Jobs without tiles are reported by a sweep of the job table in which
+    block b's producer takes jobs 64 b + lane, then every 64 G-th, G being
+    the grid.  Thousands of such jobs next to a few real ones make a grid of
+    a few blocks sweep many strides: embeds over capacity get
+    LSB_E_CAPACITY, header extracts of covers under 32 bits LSB_E_HEADER
+    with length 0, and the few real jobs match the oracle."""
+    g = inputs.rng(4451)
+    jobs = []
+    for i in range(3000):
+        if i % 500 == 7:  # a real embed or extract
+            n, k = int(g.integers(2000, 6000)), int(g.integers(1, 9))
+            op = OP_EMBED if i % 1000 == 7 else OP_EXTRACT
+        else:  # no tiles
+            op = OP_EMBED if i % 2 else OP_EXTRACT
+            k = int(g.integers(1, 9))
+            # a header extract has tiles once k n >= 32; an embed over
+            # capacity has none at any size
+            n = int(g.integers(1, 31 // k + 1)) if op == OP_EXTRACT else int(g.integers(1, 64))
+        cover = inputs.random_bytes(n, 4452, i, 1)
+        cap = oracle.capacity(n, k)
+        job = {"n": n, "k": k, "op": op, "cover": cover}
+        if op == OP_EMBED:
+            ln = max(cap, 0) + 1 if i % 500 != 7 else int(g.integers(0, cap + 1))
+            msg = inputs.random_bytes(ln, 4452, i, 2)
+            rc, want = oracle.embed(cover, msg, k)
+            job.update(msg=msg, len=ln, status=rc if rc < 0 else OK, want=want if rc == 0 else None)
+        else:
+            if cap >= 0:
+                msg = inputs.random_bytes(int(g.integers(0, cap + 1)), 4452, i, 3)
+                _, stego = oracle.embed(cover, msg, k)
+                out_cap = msg.size
+            else:
+                stego, out_cap = cover, 8
+            orc, oln, omsg = oracle.extract(stego, k, out_cap=out_cap)
+            job.update(stego=stego, msg_cap=out_cap, status=orc, len=oln, want=omsg)
+        jobs.append(job)
+    statuses = [j["status"] for j in jobs]
+    assert statuses.count(E_CAPACITY) > 1000 and statuses.count(E_HEADER) > 1000
+    plan = _run_and_check(jobs, plan=batch.Plan(len(jobs)))
+    try:
+        assert 0 < plan.tiles < 20, plan.tiles
+    finally:
+        plan.close()
+
+
 def test_plan_refuses_a_capturing_stream():
     """A plan run under stream capture would replay its table upload and
     kernel outside the plan's tracking: the call is refused before anything
