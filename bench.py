@@ -563,6 +563,25 @@ def bench_quality(api, lib_handle, cover, stego_by_k, msgs_by_k, dev, reps=5):
     b = 2 * n + 4 + msgs_by_k[1].numel()
     out["verify_k1"] = {"bytes": b, "us_median": round(us, 2), "GBps": round(b / (us * 1e-6) / 1e9, 1),
                         "mismatches": 0}
+    # embed and check through extraction in the same launch (k = 1): the
+    # algorithmic bytes are the embed's, the check runs in registers
+    ev = torch.empty_like(cover)
+    ms = []
+    for r in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        e1.record()
+        torch.cuda.synchronize()
+        lib_handle.lsb_time_next_launch(e0, e1)
+        api.embed_verify(cover, msgs_by_k[1], 1, out=ev, mismatches=cnt)
+        torch.cuda.synchronize()
+        if r:
+            ms.append(e0.elapsed_time(e1))
+    assert int(cnt.item()) == 0 and torch.equal(ev, stego_by_k[1]), "embed-verify differs from the embed"
+    del ev
+    us = sorted(ms)[len(ms) // 2] * 1e3
+    out["embed_verify_k1"] = {"bytes": b, "us_median": round(us, 2), "GBps": round(b / (us * 1e-6) / 1e9, 1),
+                              "mismatches": 0}
     pixels = n // 3
     msg = torch.empty(api.capacity(pixels, 2), dtype=torch.uint8, device=dev)
     inputs.fill_uniform(msg, 1701)

@@ -54,15 +54,27 @@ __device__ __forceinline__ uint32_t byte_wrong(const Span &s, uint64_t t, uint32
 
 // Wrong bytes of a fast vector (all 16 fields carry K stream bits): extract
 // the stego vector's fields into stream words, compare them with the stream
-// chunk w field by field, and compare the bits above the fields with the
-// cover's.
+// chunk w, and compare the bits above the fields with the cover's.  Whole
+// words first: when every word reads back and no kept bit changed (a
+// correct embedding) the vector costs a few compares; only a vector with a
+// difference is counted field by field and byte by byte.
 template <int K>
 __device__ __forceinline__ uint32_t vec_wrong(u32x4 c, u32x4 g, const uint32_t *w) {
     uint32_t got[Chunk<K>::NW];
     extract_vec<K>(g, got);
     uint32_t diff[Chunk<K>::NW];
+    uint32_t any = 0;
 #pragma unroll
-    for (int i = 0; i < Chunk<K>::NW; ++i) diff[i] = got[i] ^ w[i];
+    for (int i = 0; i < Chunk<K>::NW; ++i) {
+        diff[i] = got[i] ^ w[i];
+        any |= diff[i];
+    }
+    if constexpr (K < 8) {
+        constexpr uint32_t keep_bits = ~(((1u << K) - 1u) * 0x01010101u);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) any |= (c[d] ^ g[d]) & keep_bits;
+    }
+    if (!any) return 0;
     uint32_t bad = 0;  // bit f: byte f of the vector is wrong
 #pragma unroll
     for (int f = 0; f < 16; ++f) bad |= (get_field<K>(diff, f) != 0 ? 1u : 0u) << f;
@@ -245,7 +257,13 @@ static int verify_call(const char *name, bool embed, const uint8_t *cover, uint8
     uint64_t items = vec ? ceil_div(n, 16) : n;
     if (vec && s.inplace) items = embed_ranges(s).count;  // in place: bytes past the stream stay untouched
     uint64_t blocks = ceil_div(items ? items : 1, 256);
-    const uint64_t capb = (uint64_t)device_cus() * 8;
+    // The check alone runs a grid-stride loop over at most 8 blocks per CU.
+    // The embedding form stores, and a wave that loops waits for its
+    // previous stores each time it waits for its next loads (one counter
+    // covers both), so its grid gives every vector a thread of its own; a
+    // correct embedding adds nothing to the counter, so the larger grid
+    // costs no atomics.
+    const uint64_t capb = embed ? (uint64_t)INT32_MAX : (uint64_t)device_cus() * 8;
     if (blocks > capb) blocks = capb;
     VerifyFn fn = vec ? (embed ? fn_for_k<EmbedVerifyK>(k) : fn_for_k<VerifyK>(k))
                       : (embed ? lsb_embed_verify_bytes_kernel : lsb_verify_bytes_kernel);
