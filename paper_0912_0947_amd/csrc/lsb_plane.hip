@@ -105,10 +105,14 @@ static PlaneExtractFn plane_extract_fn(int k, uint32_t c) {
     }
 }
 
+// Grid of the plane kernels: a thread per item.  They are grid-stride
+// loops, and a looping wave's wait for its next loads also waits for its
+// previous stores; capped at 16 blocks per CU, the plane embed of an
+// 8192x8192x3 image took 70-72 us against 66-67 us uncapped (extract
+// 37.8-38.2 against 37.3-37.6 us).
 static unsigned grid_cap(uint64_t items) {
-    uint64_t blocks = ceil_div(items ? items : 1, 256);
-    const uint64_t cap = (uint64_t)device_cus() * 16;
-    return (unsigned)(blocks < cap ? blocks : cap);
+    const uint64_t blocks = ceil_div(items ? items : 1, 256);
+    return (unsigned)(blocks < (uint64_t)INT32_MAX ? blocks : (uint64_t)INT32_MAX);
 }
 
 }  // namespace lsb
