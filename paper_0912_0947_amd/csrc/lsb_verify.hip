@@ -137,35 +137,71 @@ __global__ void __launch_bounds__(256) lsb_verify_kernel(Span s, unsigned long l
     add_block_count(bad, mismatches);
 }
 
+// Embed and check one vector u of the span (any class).  A fast vector is
+// embedded in registers, stored, and its stored value is checked against
+// the stream through extraction; an edge vector is embedded byte by byte
+// and each byte this thread wrote is read back.
+template <int K>
+__device__ __forceinline__ uint32_t embed_verify_one(const Span &s, const Ranges &r, uintptr_t body_base,
+                                                     uint64_t u) {
+    if (u >= r.fast_begin && u < r.fast_end) {
+        uint32_t w[Chunk<K>::NW];
+        const uint8_t *p = reinterpret_cast<const uint8_t *>(body_base + 2 * K * u);
+        if (s.words) load_chunk_words<K>(p, w);
+        else load_chunk_bytes<K>(p, 0, w);
+        const u32x4 c = load16<true>(s.src + 16 * u);
+        const u32x4 g = embed_vec<K>(c, w);
+        store16<true>(s.dst + 16 * u, g);
+        return vec_wrong<K>(c, g, w);
+    }
+    if (u >= r.copy_begin && u < r.copy_end) {
+        if (!s.inplace) store16<true>(s.dst + 16 * u, load16<true>(s.src + 16 * u));
+        return 0;
+    }
+    uint32_t bad = 0;
+    const uint64_t t_end = 16 * u + 16 < s.n ? 16 * u + 16 : s.n;
+    for (uint64_t t = 16 * u; t < t_end; ++t) {
+        const uint32_t c = s.src[t];
+        embed_byte<K>(s, t);
+        bad += byte_wrong(s, t, c, s.dst[t]);
+    }
+    return bad;
+}
+
 // Embed and check in one launch: s.src = cover, s.dst = stego (may equal
-// cover).  Each fast vector is embedded in registers, stored, and its
-// stored value is checked against the stream through extraction.
+// cover).  A block covers 512 vectors per pass, two per thread (vectors v
+// and v + 256 of the pass, so each load instruction of a wave stays
+// contiguous); when both are fast their loads are issued before either is
+// embedded.
 template <int K>
 __global__ void __launch_bounds__(256) lsb_embed_verify_kernel(Span s, unsigned long long *mismatches) {
     const Ranges r = embed_ranges<K>(s);
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t stride = (uint64_t)gridDim.x * 512;
     const uintptr_t body_base = (uintptr_t)s.body - s.hdr_len;
     uint32_t bad = 0;
-    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < r.count; u += stride) {
-        if (u >= r.fast_begin && u < r.fast_end) {
-            uint32_t w[Chunk<K>::NW];
-            const uint8_t *p = reinterpret_cast<const uint8_t *>(body_base + 2 * K * u);
-            if (s.words) load_chunk_words<K>(p, w);
-            else load_chunk_bytes<K>(p, 0, w);
-            const u32x4 c = load16<true>(s.src + 16 * u);
-            const u32x4 g = embed_vec<K>(c, w);
-            store16<true>(s.dst + 16 * u, g);
-            bad += vec_wrong<K>(c, g, w);
-        } else if (u >= r.copy_begin && u < r.copy_end) {
-            if (!s.inplace) store16<true>(s.dst + 16 * u, load16<true>(s.src + 16 * u));
-        } else {
-            // edge vector, byte by byte: this thread's own write is read back
-            const uint64_t t_end = 16 * u + 16 < s.n ? 16 * u + 16 : s.n;
-            for (uint64_t t = 16 * u; t < t_end; ++t) {
-                const uint32_t c = s.src[t];
-                embed_byte<K>(s, t);
-                bad += byte_wrong(s, t, c, s.dst[t]);
+    for (uint64_t u0 = (uint64_t)blockIdx.x * 512 + threadIdx.x; u0 < r.count; u0 += stride) {
+        const uint64_t u1 = u0 + 256;
+        if (u0 >= r.fast_begin && u1 < r.fast_end) {
+            uint32_t w0[Chunk<K>::NW], w1[Chunk<K>::NW];
+            const uint8_t *p0 = reinterpret_cast<const uint8_t *>(body_base + 2 * K * u0);
+            const uint8_t *p1 = reinterpret_cast<const uint8_t *>(body_base + 2 * K * u1);
+            if (s.words) {
+                load_chunk_words<K>(p0, w0);
+                load_chunk_words<K>(p1, w1);
+            } else {
+                load_chunk_bytes<K>(p0, 0, w0);
+                load_chunk_bytes<K>(p1, 0, w1);
             }
+            const u32x4 c0 = load16<true>(s.src + 16 * u0);
+            const u32x4 c1 = load16<true>(s.src + 16 * u1);
+            const u32x4 g0 = embed_vec<K>(c0, w0);
+            const u32x4 g1 = embed_vec<K>(c1, w1);
+            store16<true>(s.dst + 16 * u0, g0);
+            store16<true>(s.dst + 16 * u1, g1);
+            bad += vec_wrong<K>(c0, g0, w0) + vec_wrong<K>(c1, g1, w1);
+        } else {
+            bad += embed_verify_one<K>(s, r, body_base, u0);
+            if (u1 < r.count) bad += embed_verify_one<K>(s, r, body_base, u1);
         }
     }
     add_block_count(bad, mismatches);
@@ -256,7 +292,8 @@ static int verify_call(const char *name, bool embed, const uint8_t *cover, uint8
     const bool vec = (((uintptr_t)cover | (uintptr_t)stego) & 15u) == 0;
     uint64_t items = vec ? ceil_div(n, 16) : n;
     if (vec && s.inplace) items = embed_ranges(s).count;  // in place: bytes past the stream stay untouched
-    uint64_t blocks = ceil_div(items ? items : 1, 256);
+    // the embedding kernel's blocks cover 512 vectors per pass
+    uint64_t blocks = ceil_div(items ? items : 1, vec && embed ? 512 : 256);
     // The check alone runs a grid-stride loop over at most 8 blocks per CU.
     // The embedding form stores, and a wave that loops waits for its
     // previous stores each time it waits for its next loads (one counter
