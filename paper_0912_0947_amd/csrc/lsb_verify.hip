@@ -113,25 +113,52 @@ __device__ __forceinline__ void add_block_count(uint32_t bad, unsigned long long
     }
 }
 
-// Check only: s.src = cover, s.dst = stego (read only here).
+// Check only: s.src = cover, s.dst = stego (read only here).  One vector u
+// of the span (any class).
+template <int K>
+__device__ __forceinline__ uint32_t verify_one(const Span &s, const Ranges &r, uintptr_t body_base, uint64_t u) {
+    if (u >= r.fast_begin && u < r.fast_end) {
+        uint32_t w[Chunk<K>::NW];
+        const uint8_t *p = reinterpret_cast<const uint8_t *>(body_base + 2 * K * u);
+        if (s.words) load_chunk_words<K>(p, w);
+        else load_chunk_bytes<K>(p, 0, w);
+        return vec_wrong<K>(load16<true>(s.src + 16 * u), load16<true>(s.dst + 16 * u), w);
+    }
+    if (u >= r.copy_begin && u < r.copy_end)
+        return bytes_differ(load16<true>(s.src + 16 * u), load16<true>(s.dst + 16 * u));
+    uint32_t bad = 0;
+    const uint64_t t_end = 16 * u + 16 < s.n ? 16 * u + 16 : s.n;
+    for (uint64_t t = 16 * u; t < t_end; ++t) bad += byte_wrong(s, t, s.src[t], s.dst[t]);
+    return bad;
+}
+
+// A block covers 512 vectors per pass, two per thread (vectors v and v + 256
+// of the pass), as in the embedding form below.
 template <int K>
 __global__ void __launch_bounds__(256) lsb_verify_kernel(Span s, unsigned long long *mismatches) {
     const Ranges r = embed_ranges<K>(s);  // inplace = 0: every vector is visited
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t stride = (uint64_t)gridDim.x * 512;
     const uintptr_t body_base = (uintptr_t)s.body - s.hdr_len;
     uint32_t bad = 0;
-    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < r.count; u += stride) {
-        if (u >= r.fast_begin && u < r.fast_end) {
-            uint32_t w[Chunk<K>::NW];
-            const uint8_t *p = reinterpret_cast<const uint8_t *>(body_base + 2 * K * u);
-            if (s.words) load_chunk_words<K>(p, w);
-            else load_chunk_bytes<K>(p, 0, w);
-            bad += vec_wrong<K>(load16<true>(s.src + 16 * u), load16<true>(s.dst + 16 * u), w);
-        } else if (u >= r.copy_begin && u < r.copy_end) {
-            bad += bytes_differ(load16<true>(s.src + 16 * u), load16<true>(s.dst + 16 * u));
+    for (uint64_t u0 = (uint64_t)blockIdx.x * 512 + threadIdx.x; u0 < r.count; u0 += stride) {
+        const uint64_t u1 = u0 + 256;
+        if (u0 >= r.fast_begin && u1 < r.fast_end) {
+            uint32_t w0[Chunk<K>::NW], w1[Chunk<K>::NW];
+            const uint8_t *p0 = reinterpret_cast<const uint8_t *>(body_base + 2 * K * u0);
+            const uint8_t *p1 = reinterpret_cast<const uint8_t *>(body_base + 2 * K * u1);
+            if (s.words) {
+                load_chunk_words<K>(p0, w0);
+                load_chunk_words<K>(p1, w1);
+            } else {
+                load_chunk_bytes<K>(p0, 0, w0);
+                load_chunk_bytes<K>(p1, 0, w1);
+            }
+            const u32x4 c0 = load16<true>(s.src + 16 * u0), g0 = load16<true>(s.dst + 16 * u0);
+            const u32x4 c1 = load16<true>(s.src + 16 * u1), g1 = load16<true>(s.dst + 16 * u1);
+            bad += vec_wrong<K>(c0, g0, w0) + vec_wrong<K>(c1, g1, w1);
         } else {
-            const uint64_t t_end = 16 * u + 16 < s.n ? 16 * u + 16 : s.n;
-            for (uint64_t t = 16 * u; t < t_end; ++t) bad += byte_wrong(s, t, s.src[t], s.dst[t]);
+            bad += verify_one<K>(s, r, body_base, u0);
+            if (u1 < r.count) bad += verify_one<K>(s, r, body_base, u1);
         }
     }
     add_block_count(bad, mismatches);
@@ -292,16 +319,15 @@ static int verify_call(const char *name, bool embed, const uint8_t *cover, uint8
     const bool vec = (((uintptr_t)cover | (uintptr_t)stego) & 15u) == 0;
     uint64_t items = vec ? ceil_div(n, 16) : n;
     if (vec && s.inplace) items = embed_ranges(s).count;  // in place: bytes past the stream stay untouched
-    // the embedding kernel's blocks cover 512 vectors per pass
-    uint64_t blocks = ceil_div(items ? items : 1, vec && embed ? 512 : 256);
-    // The check alone runs a grid-stride loop over at most 8 blocks per CU.
-    // The embedding form stores, and a wave that loops waits for its
-    // previous stores each time it waits for its next loads (one counter
-    // covers both), so its grid gives every vector a thread of its own; a
-    // correct embedding adds nothing to the counter, so the larger grid
-    // costs no atomics.
-    const uint64_t capb = embed ? (uint64_t)INT32_MAX : (uint64_t)device_cus() * 8;
-    if (blocks > capb) blocks = capb;
+    // The vector kernels' blocks cover 512 vectors per pass, and the grid
+    // gives every pair of vectors a thread: on a grid capped at 8 blocks
+    // per CU the waves loop, and a looping wave's wait for its next loads
+    // also waits for its previous stores (one counter covers both).  The
+    // capped grid measured slower for the check alone too.  A correct
+    // embedding adds nothing to the counter, so the larger grid costs no
+    // atomics.
+    uint64_t blocks = ceil_div(items ? items : 1, vec ? 512 : 256);
+    if (blocks > (uint64_t)INT32_MAX) blocks = (uint64_t)INT32_MAX;
     VerifyFn fn = vec ? (embed ? fn_for_k<EmbedVerifyK>(k) : fn_for_k<VerifyK>(k))
                       : (embed ? lsb_embed_verify_bytes_kernel : lsb_verify_bytes_kernel);
     hipEvent_t e0, e1;
